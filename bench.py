@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Benchmark of one H/S build on one MI355X.
+
+A step is one pass of the whole build (per-atom Cholesky and operand
+preparation, per-atom products, the large lower-triangle reductions of H and
+S, conjugate mirroring) over one synthetic k-point with inputs resident in
+HBM. The default workload is the N_G = 8000 case (N_A = 100 atoms, N_L = 81,
+complex FP64).
+
+Prints one JSON line with the FP64-equivalent TFLOP/s of the build
+(algorithmic flops / measured time), the roofline of the dominant kernel
+(the reduction, timed live with HIP events on the stream it runs on), and
+the CPU oracle timed on a bounded sample of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
+HBM_PEAK_GBS = 8000.0
+
+
+class HipEvents:
+    """Raw hipEvent_t handles from the HIP runtime torch has loaded."""
+
+    def __init__(self):
+        import torch  # noqa: F401  (binds the runtime torch ships)
+        self.rt = ctypes.CDLL("libamdhip64.so.7")
+        self.rt.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.rt.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
+                                                ctypes.c_void_p]
+        self.rt.hipEventSynchronize.argtypes = [ctypes.c_void_p]
+        self.rt.hipEventDestroy.argtypes = [ctypes.c_void_p]
+
+    def create(self, n):
+        out = []
+        for _ in range(n):
+            e = ctypes.c_void_p()
+            assert self.rt.hipEventCreate(ctypes.byref(e)) == 0
+            out.append(e.value)
+        return out
+
+    def elapsed_ms(self, a, b):
+        assert self.rt.hipEventSynchronize(ctypes.c_void_p(b)) == 0
+        ms = ctypes.c_float()
+        assert self.rt.hipEventElapsedTime(ctypes.byref(ms), ctypes.c_void_p(a), ctypes.c_void_p(b)) == 0
+        return float(ms.value)
+
+    def destroy(self, evs):
+        for e in evs:
+            self.rt.hipEventDestroy(ctypes.c_void_p(e))
+
+
+def cpu_baseline(p, seconds: float):
+    """Time the CPU oracle on the first atoms of the workload (full N_G)."""
+    import oracle
+    from paper_1611_00606_amd.flops import algorithmic_flops
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()
+                       if i.get("user_api") == "blas"] or [1])
+    except Exception:
+        threads = len(os.sched_getaffinity(0))
+
+    def run(n_atoms):
+        k = int(p.nl[:n_atoms].sum())
+        t = int((p.nl[:n_atoms].astype(np.int64) ** 2).sum())
+        t0 = time.perf_counter()
+        oracle.hamiltonian(p.A[:k], p.B[:k], p.T_AA[:t], p.T_AB[:t], p.T_BB[:t], p.nl[:n_atoms])
+        oracle.overlap(p.A[:k], p.B[:k], p.U[:k], p.nl[:n_atoms])
+        return time.perf_counter() - t0
+
+    t1 = run(1)
+    n = int(max(1, min(p.N_A, round(seconds / max(t1, 1e-3)))))
+    dt = run(n)
+    info = np.zeros(n, np.int32)
+    info[[a for a in p.failing if a < n]] = 1
+    f = algorithmic_flops(p.nl[:n], p.N_G, info)
+    return {
+        "value": f / dt / 1e12,
+        "unit": "TFLOP/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": f"direct-sum oracle (NumPy complex128) on atoms 0..{n - 1} of {p.N_A} at full "
+                  f"N_G={p.N_G}: {dt:.2f} s for {f:.3e} algorithmic flops",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="precision")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the H/S build here is a single-GPU path "
+              "(a multi-GPU sharding is described in DESIGN.md but not built). Run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from hs_inputs import make_config
+    from paper_1611_00606_amd import DeviceBuild, HS_NUM_PHASE_EVENTS
+    from paper_1611_00606_amd.flops import algorithmic_flops, reduction_flops
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    p = make_config(args.config, seed=args.seed)
+    print(f"bench: config {args.config} N_A={p.N_A} N_G={p.N_G} K={p.K}", file=sys.stderr, flush=True)
+    run = DeviceBuild.from_problem(p, device="cuda:0")
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        run.run(stream=stream)
+    torch.cuda.synchronize()
+    info = run.info.cpu().numpy()
+
+    hip = HipEvents()
+    evs = [hip.create(HS_NUM_PHASE_EVENTS) for _ in range(args.steps)]
+    t_start, t_end = hip.create(2)
+    torch.cuda.synchronize()
+    rt = hip.rt
+    rt.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    assert rt.hipEventRecord(ctypes.c_void_p(t_start), ctypes.c_void_p(stream.cuda_stream)) == 0
+    w0 = time.perf_counter()
+    for k in range(args.steps):
+        run.run(stream=stream, phase_events=evs[k])
+    assert rt.hipEventRecord(ctypes.c_void_p(t_end), ctypes.c_void_p(stream.cuda_stream)) == 0
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    total_ms = hip.elapsed_ms(t_start, t_end)
+    ms_step = total_ms / args.steps
+    phases = np.array([[hip.elapsed_ms(e[i], e[i + 1]) for i in range(HS_NUM_PHASE_EVENTS - 1)]
+                       for e in evs])
+    ph_mean = phases.mean(axis=0)
+    hip.destroy([e for es in evs for e in es] + [t_start, t_end])
+
+    f_alg = algorithmic_flops(p.nl, p.N_G, info)
+    value = f_alg / (ms_step * 1e-3) / 1e12
+    f_red = reduction_flops(p.nl, p.N_G)
+    red_ms = float(ph_mean[2])
+    achieved = f_red / (red_ms * 1e-3) / 1e12
+
+    out = {
+        "metric": "H+S build FP64-equiv TFLOP/s (% MFMA peak)",
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128 (f64)",
+        "data": "synthetic",
+        "pct_of_fp64_mfma_peak": round(100 * value / FP64_MFMA_PEAK_TFLOPS, 2),
+        "config": {
+            "workload": f"{args.config}: one k-point H+S build, N_A={p.N_A}, "
+                        f"N_L={sorted(set(p.nl.tolist()))}, N_G={p.N_G}, plain FP64 path",
+            "N_A": p.N_A, "N_L": sorted(set(p.nl.tolist())), "N_G": p.N_G, "K": p.K,
+            "failing_atoms": int((info != 0).sum()), "seed": args.seed,
+            "algorithmic_flops": f_alg,
+        },
+        "phases_ms": {
+            "prep_cholesky": round(float(ph_mean[0]), 4),
+            "atom_products": round(float(ph_mean[1]), 4),
+            "reduce_HS": round(float(ph_mean[2]), 4),
+            "mirror": round(float(ph_mean[3]), 4),
+        },
+        "wall_s_timed_region": round(wall, 3),
+        "roofline": {
+            "kernel": "k_reduce",
+            "bound": "mfma",
+            "achieved": round(achieved, 3),
+            "peak": FP64_MFMA_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4),
+            "traffic": None,
+        },
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        del run
+        torch.cuda.empty_cache()
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

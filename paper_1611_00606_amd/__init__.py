@@ -1,1 +1,25 @@
-"""MI355X-native H/S generation for FLAPW (complex FP64, gfx950 HIP kernels)."""
+"""MI355X-native generation of the FLAPW Hamiltonian and overlap matrices.
+
+The build runs in libhsbuild.so (hand-written HIP for gfx950; C ABI in
+include/hs_build.h). This package is its Python binding: marshalling of
+torch device tensors and streams into the C entry points, which keep their
+C names here.
+"""
+
+from ._binding import (  # noqa: F401
+    HS_OK,
+    HS_ERR_HIP,
+    HS_ERR_WORKSPACE,
+    HS_ERR_NOMEM,
+    HS_ERR_UNSUPPORTED,
+    HS_FP64,
+    HS_MAX_NL,
+    HSError,
+    LIB_PATH,
+    load_library,
+    hs_build,
+    hs_build_ex,
+    hs_workspace_bytes,
+    hs_status_string,
+)
+from .runner import DeviceBuild  # noqa: F401

@@ -1,0 +1,95 @@
+// Per-atom products of Alg. 1, as complex MFMA tiles:
+//   first loop     Z_a = T^BA_a A_a + 1/2 T^BB_a B_a = T_AB,a^H A_a + M2_a^H B_a
+//   second loop    W_a = M1_a^H A_a  = C_a^H A_a (success, Y_a)
+//                                    or T^AA_a A_a (failure, X_a)
+// with M1, M2 prepared by k_prep (M2 = 1/2 T^BB_a and, on failure,
+// M1 = T^AA_a, both Hermitian, so M^H = M).
+//
+// Each block computes a BM x BN tile of one atom's N_L x N_G output; the
+// contraction runs over the atom's N_L rows (twice for Z). The grid is
+// (N_G tiles, atoms x row tiles, 2 products); Z and W land in the stacked
+// [K][N_G] layout that the large reductions read.
+#include "hs_internal.h"
+#include "zmfma_tile.h"
+
+namespace hs {
+
+namespace {
+
+template <class C>
+__global__ void __launch_bounds__(C::NT)
+k_atom(Atoms at, int n_g, int mtiles, const double2 *__restrict__ A,
+       const double2 *__restrict__ B, const double2 *__restrict__ T_AB,
+       const double2 *__restrict__ M1, const double2 *__restrict__ M2,
+       double2 *__restrict__ Z, double2 *__restrict__ W) {
+    __shared__ double2 lds[C::LDS_ELEMS];
+
+    const int a = blockIdx.y / mtiles;
+    const int mt = blockIdx.y % mtiles;
+    const int which = blockIdx.z;  // 0: Z, 1: W
+    const int r0 = at.row_off[a];
+    const int n = at.row_off[a + 1] - r0;
+    const int m0 = mt * C::BM;
+    if (m0 >= n) return;  // atom has fewer rows than this row tile (mixed N_L)
+    const long long t0 = at.t_off[a];
+    const int n0 = blockIdx.x * C::BN;
+
+    SegTable<2> tab;
+    tab.ldp = n;
+    tab.ldq = n_g;
+    const double2 *Aa = A + (long long)r0 * n_g;
+    const double2 *Ba = B + (long long)r0 * n_g;
+    if (which == 0) {
+        tab.n = 2;
+        tab.s[0] = Seg{T_AB + t0, nullptr, nullptr, Aa, nullptr, n};
+        tab.s[1] = Seg{M2 + t0, nullptr, nullptr, Ba, nullptr, n};
+    } else {
+        tab.n = 1;
+        tab.s[0] = Seg{M1 + t0, nullptr, nullptr, Aa, nullptr, n};
+        tab.s[1] = Seg{nullptr, nullptr, nullptr, nullptr, nullptr, 0};
+    }
+    const int ktot = which == 0 ? 2 * n : n;
+
+    Acc<C> acc;
+    ztile_run<C, 2>(tab, ktot, m0, n, n0, n_g, acc, lds);
+
+    double2 *out = (which == 0 ? Z : W) + (long long)r0 * n_g;
+#pragma unroll
+    for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+        for (int j = 0; j < C::TN; ++j) {
+            const int g = n0 + acc_col<C>(j);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int l = m0 + acc_row<C>(i, v);
+                if (l < n && g < n_g) out[(long long)l * n_g + g] = double2{acc.re[i][j][v], acc.im[i][j][v]};
+            }
+        }
+}
+
+// Row tile of 64 for N_L <= 64, else 128 (one tile covers an atom's rows).
+using AtomCfg64 = TileCfg<64, 64, 16, 2, 2>;
+using AtomCfg128 = TileCfg<128, 64, 16, 2, 2>;
+
+template <class C>
+hipError_t launch_atom_cfg(const Atoms &at, int n_g, const double2 *A, const double2 *B,
+                           const double2 *T_AB, const double2 *M1, const double2 *M2,
+                           double2 *Z, double2 *W, hipStream_t st) {
+    const int mtiles = (at.max_nl + C::BM - 1) / C::BM;
+    dim3 grid((n_g + C::BN - 1) / C::BN, at.n_atoms * mtiles, 2);
+    hipLaunchKernelGGL(k_atom<C>, grid, dim3(C::NT), 0, st, at, n_g, mtiles, A, B, T_AB, M1,
+                       M2, Z, W);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_atom(const Atoms &at, int n_g, const double2 *A, const double2 *B,
+                       const double2 *T_AB, const double2 *M1, const double2 *M2,
+                       double2 *Z, double2 *W, hipStream_t st) {
+    if (at.max_nl <= 64)
+        return launch_atom_cfg<AtomCfg64>(at, n_g, A, B, T_AB, M1, M2, Z, W, st);
+    return launch_atom_cfg<AtomCfg128>(at, n_g, A, B, T_AB, M1, M2, Z, W, st);
+}
+
+}  // namespace hs

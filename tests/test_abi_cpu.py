@@ -1,0 +1,111 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point the header declares, sizes its workspace, and rejects bad
+arguments with LAPACK-style codes before touching the device."""
+
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_1611_00606_amd as P
+from paper_1611_00606_amd import _binding as Bd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
+           if f.endswith(".h")]
+
+
+def _declared():
+    names = set()
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(hs_\w+)\s*\(", text, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for want in ("hs_build", "hs_build_ex", "hs_workspace_bytes", "hs_status_string"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = P.load_library()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", P.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {l.split()[-1] for l in out.splitlines() if l.strip()}
+    for name in _declared():
+        assert name in exported, name
+
+
+def test_workspace_bytes():
+    K, ng = 100 * 81, 8000
+    ws = P.hs_workspace_bytes(100, None, 81, ng)
+    assert ws >= 2 * 16 * K * ng            # Z and W stacks
+    assert ws < 2 * 16 * K * ng + (64 << 20)
+    nl = [16, 49, 81, 121]
+    ws_mixed = P.hs_workspace_bytes(4, nl, 0, 6000)
+    assert ws_mixed >= 2 * 16 * sum(nl) * 6000
+    assert P.hs_workspace_bytes(0, None, 16, 100) == 0
+    assert P.hs_workspace_bytes(1, None, 129, 100) == 0
+    assert P.hs_workspace_bytes(2, [16, 0], 16, 100) == 0
+    assert P.hs_workspace_bytes(1, None, 16, 0) == 0
+    assert P.hs_workspace_bytes(1, None, 16, 10, 7) == 0
+
+
+FAKE = 0x1000  # never dereferenced: argument checks return first
+
+
+def _hs_build(*args):
+    lib = P.load_library()
+    return lib.hs_build(*args)
+
+
+@pytest.mark.parametrize("pos", range(6))
+def test_null_input_pointer(pos):
+    ptrs = [FAKE] * 6
+    ptrs[pos] = None
+    assert _hs_build(*ptrs, 2, 4, 8, FAKE, FAKE) == -(pos + 1)
+
+
+@pytest.mark.parametrize("n_a,n_l,n_g,code", [(0, 4, 8, -7), (-3, 4, 8, -7), (2, 0, 8, -8),
+                                              (2, 129, 8, -8), (2, 4, 0, -9)])
+def test_bad_sizes(n_a, n_l, n_g, code):
+    assert _hs_build(*[FAKE] * 6, n_a, n_l, n_g, FAKE, FAKE) == code
+
+
+def test_null_outputs():
+    assert _hs_build(*[FAKE] * 6, 2, 4, 8, None, FAKE) == -10
+    assert _hs_build(*[FAKE] * 6, 2, 4, 8, FAKE, None) == -11
+
+
+def test_build_ex_option_checks():
+    lib = P.load_library()
+    assert lib.hs_build_ex(*[FAKE] * 6, 2, 4, 8, FAKE, FAKE, None) == -12
+    opt = Bd.hs_options()
+    opt.mode = 5
+    assert lib.hs_build_ex(*[FAKE] * 6, 2, 4, 8, FAKE, FAKE, ctypes.byref(opt)) == -12
+    nl = np.array([4, 200], np.int32)
+    opt = Bd.hs_options()
+    opt.nl_per_atom = nl.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    assert lib.hs_build_ex(*[FAKE] * 6, 2, 0, 8, FAKE, FAKE, ctypes.byref(opt)) == -8
+
+
+def test_status_strings():
+    assert P.hs_status_string(0) == "success"
+    assert "workspace" in P.hs_status_string(2)
+    assert "argument" in P.hs_status_string(-3)
+
+
+def test_binding_rejects_host_tensors():
+    import torch
+    t = torch.zeros(4, dtype=torch.complex128)
+    with pytest.raises(ValueError):
+        P.hs_build(t, t, t, t, t, t, 1, 2, 2, t, t)
