@@ -221,12 +221,14 @@ __device__ __forceinline__ void ztile_run(const SegTable<NSEG> &table, int ktot,
     }
 }
 
-// Output coordinates of accumulator element v of block (i, j) for this lane:
-// the 16x16 FP64 MFMA result holds D[4*(lane/16) + v][lane % 16].
+// Output coordinates of accumulator element v of block (i, j) for this lane.
+// Operand layouts of V_MFMA_F64_16X16X4_F64: lane l holds A[l % 16][l / 16]
+// and B[l / 16][l % 16]; result element v of lane l is D[4 v + l / 16][l % 16]
+// (measured on gfx950 with a one-wave probe of known integer operands).
 template <class C>
 __device__ __forceinline__ int acc_row(int i, int v) {
     const int wave = threadIdx.x >> 6;
-    return (wave % C::WM) * C::WTM + i * 16 + 4 * ((threadIdx.x & 63) >> 4) + v;
+    return (wave % C::WM) * C::WTM + i * 16 + 4 * v + ((threadIdx.x & 63) >> 4);
 }
 template <class C>
 __device__ __forceinline__ int acc_col(int j) {
