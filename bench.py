@@ -32,6 +32,30 @@ FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
 HBM_PEAK_GBS = 8000.0
 
 
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_reduce_precision_ng8000.md")
+TRAFFIC_SOURCES = ["paper_1611_00606_amd/csrc/zmfma_tile.h", "paper_1611_00606_amd/csrc/k_reduce.hip"]
+
+
+def measured_traffic(config: str):
+    """HBM bytes per k_reduce launch from the committed rocprofv3 counter
+    record, or None when the record is for another workload or the kernel's
+    sources have changed since the counters were taken."""
+    import hashlib
+    if config != "precision" or not os.path.exists(TRAFFIC_RECORD):
+        return None
+    rec = {}
+    for line in open(TRAFFIC_RECORD):
+        if ":" in line and line.split(":")[0] in ("source_sha256", "traffic_bytes"):
+            k, v = line.split(":", 1)
+            rec[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if rec.get("source_sha256") != h.hexdigest() or "traffic_bytes" not in rec:
+        return None
+    return float(rec["traffic_bytes"])
+
+
 class HipEvents:
     """Raw hipEvent_t handles from the HIP runtime torch has loaded."""
 
@@ -205,7 +229,8 @@ def main():
             "peak": FP64_MFMA_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(args.config),
+            "traffic_unit": "HBM bytes per k_reduce launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-calibrated)",
         },
         "cpu_baseline": None,
     }

@@ -113,8 +113,8 @@ struct Plan {
         size_t o = 0;
         o_tables = o; o = align_up(o + sizeof(int) * tables.size());
         o_info = o;   o = align_up(o + sizeof(int) * (size_t)N_A);
-        o_sel = o;    o = align_up(o + sizeof(int) * (size_t)K);
-        o_d = o;      o = align_up(o + sizeof(double) * (size_t)K);
+        o_sel = o;    o = align_up(o + sizeof(int) * 3 * (size_t)K);
+        o_d = o;      o = align_up(o + sizeof(double) * 2 * (size_t)K);
         o_m1 = o;     o = align_up(o + 16 * (size_t)t_total);
         o_m2 = o;     o = align_up(o + 16 * (size_t)t_total);
         o_z = o;      o = align_up(o + 16 * (size_t)K * (size_t)N_G);

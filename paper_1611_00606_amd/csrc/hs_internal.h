@@ -22,8 +22,11 @@ struct Atoms {
 //   M1_a      C_a (lower, zero above) on success, else T_AA,a as a full
 //             Hermitian matrix from its lower triangle
 //   M2_a      1/2 T_BB,a as a full Hermitian matrix from its lower triangle
-//   d[r]      |U[r]|^2
-//   sel[r]    1 when row r belongs to an atom on the failure branch
+//   d[2K]     per contraction row of the S reduction (A rows, then B rows):
+//             d[r] = 1, d[K + r] = |U[r]|^2
+//   sel[3K]   per contraction row of the H reduction (Z, B, then W rows):
+//             sel[r] = sel[K + r] = 0, sel[2K + r] = 1 when row r belongs to
+//             an atom on the failure branch (its left operand is then A)
 hipError_t launch_prep(const Atoms &at, const double2 *T_AA, const double2 *T_BB,
                        const double2 *U, double2 *M1, double2 *M2, double *d,
                        int *sel, int *info, hipStream_t st);

@@ -34,24 +34,31 @@ k_atom(Atoms at, int n_g, int mtiles, const double2 *__restrict__ A,
     const long long t0 = at.t_off[a];
     const int n0 = blockIdx.x * C::BN;
 
-    SegTable<2> tab;
-    tab.ldp = n;
-    tab.ldq = n_g;
     const double2 *Aa = A + (long long)r0 * n_g;
     const double2 *Ba = B + (long long)r0 * n_g;
+    Segs<2, false, false> tab;
+    tab.ldp = n;
+    tab.ldq = n_g;
+    tab.len = n;
+    tab.palt = nullptr;
+    tab.sel = nullptr;
+    tab.qscale = nullptr;
     if (which == 0) {
-        tab.n = 2;
-        tab.s[0] = Seg{T_AB + t0, nullptr, nullptr, Aa, nullptr, n};
-        tab.s[1] = Seg{M2 + t0, nullptr, nullptr, Ba, nullptr, n};
+        tab.nseg = 2;
+        tab.P[0] = T_AB + t0;
+        tab.Q[0] = Aa;
+        tab.P[1] = M2 + t0;
+        tab.Q[1] = Ba;
     } else {
-        tab.n = 1;
-        tab.s[0] = Seg{M1 + t0, nullptr, nullptr, Aa, nullptr, n};
-        tab.s[1] = Seg{nullptr, nullptr, nullptr, nullptr, nullptr, 0};
+        tab.nseg = 1;
+        tab.P[0] = M1 + t0;
+        tab.Q[0] = Aa;
+        tab.P[1] = M1 + t0;
+        tab.Q[1] = Aa;
     }
-    const int ktot = which == 0 ? 2 * n : n;
 
     Acc<C> acc;
-    ztile_run<C, 2>(tab, ktot, m0, n, n0, n_g, acc, lds);
+    ztile_run<C>(tab, m0, n, n0, n_g, acc, lds);
 
     double2 *out = (which == 0 ? Z : W) + (long long)r0 * n_g;
 #pragma unroll

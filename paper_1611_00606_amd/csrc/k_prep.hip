@@ -134,10 +134,14 @@ k_prep(Atoms at, const double2 *__restrict__ T_AA, const double2 *__restrict__ T
         v.y *= 0.5;
         m2[e] = v;
     }
+    const int K = at.K;
     for (int l = tid; l < n; l += PREP_THREADS) {
         const double2 u = U[r0 + l];
-        d[r0 + l] = u.x * u.x + u.y * u.y;
-        sel[r0 + l] = info != 0;
+        d[r0 + l] = 1.0;
+        d[K + r0 + l] = u.x * u.x + u.y * u.y;
+        sel[r0 + l] = 0;
+        sel[K + r0 + l] = 0;
+        sel[2 * K + r0 + l] = info != 0;
     }
     if (tid == 0) info_out[a] = info;
 }

@@ -24,8 +24,28 @@ namespace hs {
 
 namespace {
 
-using RedCfg = TileCfg<128, 128, 16, 2, 4>;
-constexpr int BAND = 4;   // tile columns per band of the tile order
+// Tile shape of the reductions (overridable at build time for tuning sweeps).
+#ifndef HS_RED_BM
+#define HS_RED_BM 128
+#endif
+#ifndef HS_RED_BN
+#define HS_RED_BN 128
+#endif
+#ifndef HS_RED_BK
+#define HS_RED_BK 16
+#endif
+#ifndef HS_RED_WM
+#define HS_RED_WM 2
+#endif
+#ifndef HS_RED_WN
+#define HS_RED_WN 4
+#endif
+#ifndef HS_RED_BAND
+#define HS_RED_BAND 4
+#endif
+using RedCfg = TileCfg<HS_RED_BM, HS_RED_BN, HS_RED_BK, HS_RED_WM, HS_RED_WN>;
+static_assert(HS_RED_BM == HS_RED_BN, "lower-triangle tiling needs square tiles");
+constexpr int BAND = HS_RED_BAND;   // tile columns per band of the tile order
 
 struct RedArgs {
     const double2 *A, *B, *Z, *W;
@@ -91,23 +111,37 @@ k_reduce(RedArgs args) {
     // Segment tables are built from scalar arguments in registers: taking a
     // reference into the by-value kernel argument would copy it to scratch.
     const long long ld = args.n_g;
-    const int K = args.K;
     Acc<C> acc;
     if (isH) {
-        SegTable<3> t;
-        t.n = 3;
+        // Z^H B + B^H Z + (W or A)^H W
+        Segs<3, true, false> t;
+        t.nseg = 3;
+        t.len = args.K;
         t.ldp = t.ldq = ld;
-        t.s[0] = Seg{args.Z, nullptr, nullptr, args.B, nullptr, K};
-        t.s[1] = Seg{args.B, nullptr, nullptr, args.Z, nullptr, K};
-        t.s[2] = Seg{args.W, args.A, args.sel, args.W, nullptr, K};
-        ztile_run<C, 3>(t, 3 * K, m0, args.n_g, n0, args.n_g, acc, lds);
+        t.P[0] = args.Z;
+        t.Q[0] = args.B;
+        t.P[1] = args.B;
+        t.Q[1] = args.Z;
+        t.P[2] = args.W;
+        t.Q[2] = args.W;
+        t.palt = args.A;
+        t.sel = args.sel;      // [3K]: 0 on the first two segments
+        t.qscale = nullptr;
+        ztile_run<C>(t, m0, args.n_g, n0, args.n_g, acc, lds);
     } else {
-        SegTable<2> t;
-        t.n = 2;
+        // A^H A + B^H diag(|u|^2) B
+        Segs<2, false, true> t;
+        t.nseg = 2;
+        t.len = args.K;
         t.ldp = t.ldq = ld;
-        t.s[0] = Seg{args.A, nullptr, nullptr, args.A, nullptr, K};
-        t.s[1] = Seg{args.B, nullptr, nullptr, args.B, args.d, K};
-        ztile_run<C, 2>(t, 2 * K, m0, args.n_g, n0, args.n_g, acc, lds);
+        t.P[0] = args.A;
+        t.Q[0] = args.A;
+        t.P[1] = args.B;
+        t.Q[1] = args.B;
+        t.palt = nullptr;
+        t.sel = nullptr;
+        t.qscale = args.d;     // [2K]: 1 on A's rows, |u|^2 on B's rows
+        ztile_run<C>(t, m0, args.n_g, n0, args.n_g, acc, lds);
     }
 
     double2 *out = isH ? args.H : args.S;
