@@ -122,6 +122,66 @@ def cpu_baseline(p, seconds: float):
     }
 
 
+def serving_bench(seed: int, n_slots: int = 4, arena_gb: float = 24.0, n_sets: int = 4,
+                  load: float = 0.8):
+    """Serving form: 64 k-point requests on one resident atom set (64 atoms,
+    N_L = 64), N_G integer-uniform in [1500, 9000], Poisson arrivals at
+    `load` / (mean latency of a request served alone), continuous batching
+    on `n_slots` streams with admission by device footprint into an arena of
+    `arena_gb` GB. Inputs come from `n_sets` seeded (A, B) pairs held in
+    pinned host memory; request r takes the first N_G columns of pair r mod
+    n_sets and copies them to the device as part of its service."""
+    import torch
+    from hs_inputs import serving_arrivals, serving_atoms, serving_request_ab, serving_requests
+    from paper_1611_00606_amd.flops import algorithmic_flops
+    from paper_1611_00606_amd.serving import Context, ServingLoop, percentile, summarize
+
+    atoms = serving_atoms(seed)
+    ctx = Context(atoms.T_AA, atoms.T_AB, atoms.T_BB, atoms.U, atoms.nl)
+    info = ctx.info()
+    sizes = [int(x) for x in serving_requests(seed)]
+    ng_max = max(sizes)
+    pool = []
+    for j in range(n_sets):
+        A, B = serving_request_ab(seed, j, ng_max, ctx.K)
+        pa = torch.empty(A.shape, dtype=torch.complex128, pin_memory=True)
+        pb = torch.empty(B.shape, dtype=torch.complex128, pin_memory=True)
+        pa.numpy()[...] = A
+        pb.numpy()[...] = B
+        pool.append((pa, pb))
+        del A, B
+    reqs = [{"id": r, "N_G": n, "A_ptr": pool[r % n_sets][0].data_ptr(),
+             "B_ptr": pool[r % n_sets][1].data_ptr(), "ld": ng_max} for r, n in enumerate(sizes)]
+    arena = int(arena_gb * 1e9)
+    loop = ServingLoop(ctx, n_slots, arena)
+    # calibration: a spread of requests served one at a time
+    cal_ids = [int(i) for i in np.argsort(sizes)[np.linspace(0, len(sizes) - 1, 8).astype(int)]]
+    alone = []
+    for i in cal_ids:
+        rec = loop.run([dict(reqs[i], id=1000 + i)], [0.0])
+        alone.append(rec[0]["latency"])
+    mean_alone = float(np.mean(alone))
+    rate = load / mean_alone
+    arrivals = serving_arrivals(seed, len(reqs), rate) - serving_arrivals(seed, len(reqs), rate)[0]
+    recs = loop.run(reqs, arrivals)
+    peak = loop.peak_bytes
+    loop.close()
+    ctx.close()
+    out = summarize(recs, lambda n: algorithmic_flops(atoms.nl, n, info))
+    out.update({
+        "mode": "fp64",
+        "workload": "64 requests, N_A=64 atoms, N_L=64, N_G uniform in [1500, 9000], Poisson arrivals",
+        "arrival_rate_per_s": rate,
+        "load": load,
+        "alone_mean_latency_ms": 1e3 * mean_alone,
+        "alone_p99_latency_ms": 1e3 * percentile(alone, 99),
+        "n_slots": n_slots,
+        "arena_gb": arena_gb,
+        "peak_arena_gb": peak / 1e9,
+    })
+    return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in out.items()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +191,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving-form measurement (k-point builds/s, p50/p99)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run one plain device copy of MIB MiB (to scale HBM byte "
                          "counters against a kernel of known traffic) and exit")
@@ -234,10 +296,13 @@ def main():
         },
         "cpu_baseline": None,
     }
+    del run
+    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        del run
-        torch.cuda.empty_cache()
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+    if not args.no_serving:
+        print("bench: serving stream", file=sys.stderr, flush=True)
+        out["serving"] = serving_bench(args.seed)
     print(json.dumps(out), flush=True)
 
 

@@ -155,6 +155,116 @@ int hs_build_ex(const hs_complex *A, const hs_complex *B,
 /* Human-readable text for a status code (thread-local last HIP message for 1). */
 const char *hs_status_string(int status);
 
+/* ------------------------------------------------------------------------
+ * Resident context: one atom set, many k-points.
+ *
+ * T^[..]_a and U_a do not depend on the k-point, while A_a, B_a do: there is
+ * one (H, S) pair per independent k-point (Sec. 1.1). The context keeps the
+ * atom side on the device and runs the k-independent part of Alg. 1 once:
+ * the per-atom Cholesky of T^AA_a with its failure flags (second loop's try
+ * step) and the operand forms of the per-atom products. Each k-point then
+ * runs only the per-atom products and the large reductions.
+ * ---------------------------------------------------------------------- */
+typedef struct hs_ctx hs_ctx;
+
+/*
+ * hs_ctx_create - copy the atom data into a new context and factorize.
+ * Arguments: 1 T_AA, 2 T_AB, 3 T_BB, 4 U (device, layouts as above),
+ * 5 N_A >= 1, 6 N_L (uniform N_L, ignored when 7 is given), 7 nl_per_atom
+ * (HOST int32 [N_A] or NULL), 8 stream (hipStream_t or NULL), 9 out.
+ * Synchronous: returns after the context is ready (inputs may be freed
+ * afterwards). The context owns its device memory until hs_ctx_destroy.
+ */
+int hs_ctx_create(const hs_complex *T_AA, const hs_complex *T_AB, const hs_complex *T_BB,
+                  const hs_complex *U, int N_A, int N_L, const int32_t *nl_per_atom,
+                  void *stream, hs_ctx **out);
+
+/* Rows K = sum_a N_L(a) of the A, B operands this context expects. */
+int hs_ctx_rows(const hs_ctx *ctx);
+
+/* Per-atom failure flags (as hs_options.info) copied to HOST int32 [N_A]. */
+int hs_ctx_info(const hs_ctx *ctx, int32_t *info_host);
+
+/* Device scratch that hs_ctx_build needs for N_G (0 for invalid sizes). */
+size_t hs_ctx_workspace_bytes(const hs_ctx *ctx, int N_G, int mode);
+
+/* Device bytes one k-point occupies: A, B, H, S and the workspace. This is
+ * what the serving loop admits requests by. */
+size_t hs_ctx_footprint_bytes(const hs_ctx *ctx, int N_G, int mode);
+
+/*
+ * hs_ctx_build - enqueue one k-point on opt->stream (asynchronous, like
+ * hs_build_ex). Arguments: 1 ctx, 2 A, 3 B ([K][N_G] device), 4 N_G >= 1,
+ * 5 H, 6 S ([N_G][N_G] device), 7 opt (stream, workspace, mode,
+ * phase_events are used; info and nl_per_atom are ignored: the context
+ * holds them). Concurrent calls on different streams with different
+ * workspaces and outputs are allowed; results are bitwise identical to a
+ * build of the same inputs alone.
+ */
+int hs_ctx_build(const hs_ctx *ctx, const hs_complex *A, const hs_complex *B, int N_G,
+                 hs_complex *H, hs_complex *S, const hs_options *opt);
+
+void hs_ctx_destroy(hs_ctx *ctx);
+
+/* ------------------------------------------------------------------------
+ * Serving loop: continuous batching of k-point builds on one context.
+ *
+ * Requests (one k-point each, any N_G) are queued on submit and admitted in
+ * arrival order as soon as a slot (a HIP stream) is free and their device
+ * footprint (hs_ctx_footprint_bytes) fits in the free part of the server's
+ * device arena. An admitted request copies its A, B from host memory, builds
+ * on its slot's stream, and keeps H, S in the arena until released, so work
+ * of several requests overlaps on the device. All calls are host-side and
+ * non-blocking except hs_server_destroy; one thread drives a server.
+ * ---------------------------------------------------------------------- */
+typedef struct hs_server hs_server;
+
+typedef struct {
+    int64_t id;                 /* caller's tag, unique among live requests */
+    int N_G;                    /* >= 1 */
+    const hs_complex *A_host;   /* HOST [K][ld] (pinned memory lets the copy overlap) */
+    const hs_complex *B_host;   /* HOST [K][ld]; the first N_G columns are used */
+    int64_t ld;                 /* row stride of A_host, B_host in elements, >= N_G */
+} hs_request;
+
+typedef struct {
+    int64_t id;
+    int N_G;
+    int status;                 /* 0, or the error status of the request */
+    hs_complex *H, *S;          /* device [N_G][N_G], valid until hs_server_release */
+    double t_submit, t_admit, t_done;   /* seconds on the server clock (hs_server_now) */
+} hs_result;
+
+/* Arguments: 1 ctx (must outlive the server), 2 n_slots >= 1,
+ * 3 arena_bytes (device memory reserved once, here), 4 mode, 5 out. */
+int hs_server_create(hs_ctx *ctx, int n_slots, size_t arena_bytes, int mode, hs_server **out);
+
+/* Queue a request (host memory must stay valid until its result is popped).
+ * Returns HS_ERR_NOMEM (3) when its footprint exceeds the whole arena. */
+int hs_server_submit(hs_server *srv, const hs_request *req);
+
+/* Admit and launch what fits, collect completions; returns the number of
+ * completed results waiting to be popped, or a negative status on error. */
+int hs_server_progress(hs_server *srv);
+
+/* Pop one completed result into *out: returns 1, or 0 when none is ready. */
+int hs_server_pop(hs_server *srv, hs_result *out);
+
+/* Free the arena space of a popped result (its H, S become invalid). */
+int hs_server_release(hs_server *srv, int64_t id);
+
+/* Requests queued, in flight, or completed but not yet popped. */
+int hs_server_pending(const hs_server *srv);
+
+/* Device bytes currently held (admitted or unreleased requests). */
+size_t hs_server_used_bytes(const hs_server *srv);
+
+/* Seconds since the server was created (monotonic clock). */
+double hs_server_now(const hs_server *srv);
+
+/* Waits for all launched work, then frees the arena and streams. */
+void hs_server_destroy(hs_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

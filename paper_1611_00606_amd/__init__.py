@@ -23,4 +23,22 @@ from ._binding import (  # noqa: F401
     hs_workspace_bytes,
     hs_status_string,
 )
-from .runner import DeviceBuild  # noqa: F401
+from ._binding import (  # noqa: F401,E402
+    hs_ctx_create,
+    hs_ctx_rows,
+    hs_ctx_info,
+    hs_ctx_workspace_bytes,
+    hs_ctx_footprint_bytes,
+    hs_ctx_build,
+    hs_ctx_destroy,
+    hs_server_create,
+    hs_server_submit,
+    hs_server_progress,
+    hs_server_pop,
+    hs_server_release,
+    hs_server_pending,
+    hs_server_used_bytes,
+    hs_server_now,
+    hs_server_destroy,
+)
+from .runner import DeviceBuild  # noqa: F401,E402

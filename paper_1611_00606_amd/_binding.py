@@ -46,6 +46,29 @@ class hs_options(ctypes.Structure):
     ]
 
 
+class hs_request(ctypes.Structure):
+    _fields_ = [
+        ("id", ctypes.c_int64),
+        ("N_G", ctypes.c_int),
+        ("A_host", ctypes.c_void_p),
+        ("B_host", ctypes.c_void_p),
+        ("ld", ctypes.c_int64),
+    ]
+
+
+class hs_result(ctypes.Structure):
+    _fields_ = [
+        ("id", ctypes.c_int64),
+        ("N_G", ctypes.c_int),
+        ("status", ctypes.c_int),
+        ("H", ctypes.c_void_p),
+        ("S", ctypes.c_void_p),
+        ("t_submit", ctypes.c_double),
+        ("t_admit", ctypes.c_double),
+        ("t_done", ctypes.c_double),
+    ]
+
+
 _lib = None
 
 
@@ -72,6 +95,40 @@ def load_library() -> ctypes.CDLL:
     lib.hs_workspace_bytes.restype = ctypes.c_size_t
     lib.hs_status_string.argtypes = [i32]
     lib.hs_status_string.restype = ctypes.c_char_p
+    sz = ctypes.c_size_t
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    lib.hs_ctx_create.argtypes = [vp] * 4 + [i32, i32, i32p, vp, ctypes.POINTER(vp)]
+    lib.hs_ctx_create.restype = i32
+    lib.hs_ctx_rows.argtypes = [vp]
+    lib.hs_ctx_rows.restype = i32
+    lib.hs_ctx_info.argtypes = [vp, i32p]
+    lib.hs_ctx_info.restype = i32
+    lib.hs_ctx_workspace_bytes.argtypes = [vp, i32, i32]
+    lib.hs_ctx_workspace_bytes.restype = sz
+    lib.hs_ctx_footprint_bytes.argtypes = [vp, i32, i32]
+    lib.hs_ctx_footprint_bytes.restype = sz
+    lib.hs_ctx_build.argtypes = [vp, vp, vp, i32, vp, vp, ctypes.POINTER(hs_options)]
+    lib.hs_ctx_build.restype = i32
+    lib.hs_ctx_destroy.argtypes = [vp]
+    lib.hs_ctx_destroy.restype = None
+    lib.hs_server_create.argtypes = [vp, i32, sz, i32, ctypes.POINTER(vp)]
+    lib.hs_server_create.restype = i32
+    lib.hs_server_submit.argtypes = [vp, ctypes.POINTER(hs_request)]
+    lib.hs_server_submit.restype = i32
+    lib.hs_server_progress.argtypes = [vp]
+    lib.hs_server_progress.restype = i32
+    lib.hs_server_pop.argtypes = [vp, ctypes.POINTER(hs_result)]
+    lib.hs_server_pop.restype = i32
+    lib.hs_server_release.argtypes = [vp, ctypes.c_int64]
+    lib.hs_server_release.restype = i32
+    lib.hs_server_pending.argtypes = [vp]
+    lib.hs_server_pending.restype = i32
+    lib.hs_server_used_bytes.argtypes = [vp]
+    lib.hs_server_used_bytes.restype = sz
+    lib.hs_server_now.argtypes = [vp]
+    lib.hs_server_now.restype = ctypes.c_double
+    lib.hs_server_destroy.argtypes = [vp]
+    lib.hs_server_destroy.restype = None
     _lib = lib
     return lib
 
@@ -163,3 +220,115 @@ def hs_build_ex(A, B, T_AA, T_AB, T_BB, U, N_A, N_L, N_G, H, S, *, workspace,
                                     ctypes.byref(opt))
     del arr
     return _raise(rc, check)
+
+
+# ---------------------------------------------------------------------------
+# Resident context and serving loop
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return stream if isinstance(stream, int) else stream.cuda_stream
+
+
+def hs_ctx_create(T_AA, T_AB, T_BB, U, N_A, N_L, nl_per_atom=None, stream=None) -> int:
+    """Create a resident context; returns its handle (synchronous)."""
+    _check_c128(T_AA, T_AB, T_BB, U)
+    arr, p = _nl_array(nl_per_atom)
+    out = ctypes.c_void_p()
+    rc = load_library().hs_ctx_create(_ptr(T_AA), _ptr(T_AB), _ptr(T_BB), _ptr(U), int(N_A),
+                                      int(N_L), p, _stream_handle(stream), ctypes.byref(out))
+    del arr
+    _raise(rc, True)
+    return out.value
+
+
+def hs_ctx_rows(ctx) -> int:
+    return int(load_library().hs_ctx_rows(ctx))
+
+
+def hs_ctx_info(ctx, N_A) -> np.ndarray:
+    info = np.zeros(int(N_A), np.int32)
+    rc = load_library().hs_ctx_info(ctx, info.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    _raise(rc, True)
+    return info
+
+
+def hs_ctx_workspace_bytes(ctx, N_G, mode=HS_FP64) -> int:
+    return int(load_library().hs_ctx_workspace_bytes(ctx, int(N_G), int(mode)))
+
+
+def hs_ctx_footprint_bytes(ctx, N_G, mode=HS_FP64) -> int:
+    return int(load_library().hs_ctx_footprint_bytes(ctx, int(N_G), int(mode)))
+
+
+def hs_ctx_build(ctx, A, B, N_G, H, S, *, workspace, stream=None, mode=HS_FP64,
+                 phase_events=None, check=True) -> int:
+    _check_c128(A, B, H, S)
+    opt = hs_options()
+    opt.stream = _stream_handle(stream)
+    opt.workspace = _ptr(workspace)
+    opt.workspace_bytes = workspace.numel() * workspace.element_size()
+    opt.mode = int(mode)
+    ev = None
+    if phase_events is not None:
+        ev = (ctypes.c_void_p * HS_NUM_PHASE_EVENTS)(*phase_events)
+        opt.phase_events = ctypes.cast(ev, ctypes.POINTER(ctypes.c_void_p))
+    rc = load_library().hs_ctx_build(ctx, _ptr(A), _ptr(B), int(N_G), _ptr(H), _ptr(S),
+                                     ctypes.byref(opt))
+    return _raise(rc, check)
+
+
+def hs_ctx_destroy(ctx) -> None:
+    load_library().hs_ctx_destroy(ctx)
+
+
+def hs_server_create(ctx, n_slots, arena_bytes, mode=HS_FP64) -> int:
+    out = ctypes.c_void_p()
+    rc = load_library().hs_server_create(ctx, int(n_slots), int(arena_bytes), int(mode),
+                                         ctypes.byref(out))
+    _raise(rc, True)
+    return out.value
+
+
+def hs_server_submit(srv, rid, N_G, A_host_ptr, B_host_ptr, ld, check=True) -> int:
+    req = hs_request(int(rid), int(N_G), A_host_ptr, B_host_ptr, int(ld))
+    return _raise(load_library().hs_server_submit(srv, ctypes.byref(req)), check)
+
+
+def hs_server_progress(srv) -> int:
+    n = load_library().hs_server_progress(srv)
+    if n < 0:
+        raise HSError(n, hs_status_string(n))
+    return n
+
+
+def hs_server_pop(srv):
+    """The next completed result as a dict, or None."""
+    r = hs_result()
+    if load_library().hs_server_pop(srv, ctypes.byref(r)) != 1:
+        return None
+    return {"id": r.id, "N_G": r.N_G, "status": r.status, "H": r.H, "S": r.S,
+            "t_submit": r.t_submit, "t_admit": r.t_admit, "t_done": r.t_done}
+
+
+def hs_server_release(srv, rid) -> int:
+    return _raise(load_library().hs_server_release(srv, int(rid)), True)
+
+
+def hs_server_pending(srv) -> int:
+    return int(load_library().hs_server_pending(srv))
+
+
+def hs_server_used_bytes(srv) -> int:
+    return int(load_library().hs_server_used_bytes(srv))
+
+
+def hs_server_now(srv) -> float:
+    return float(load_library().hs_server_now(srv))
+
+
+def hs_server_destroy(srv) -> None:
+    load_library().hs_server_destroy(srv)

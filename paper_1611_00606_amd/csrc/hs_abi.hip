@@ -1,11 +1,13 @@
 // C ABI of the H/S builder: argument checks, planning (atom tables and the
 // workspace carve), and the launch sequence of one build:
+//   k_tables  per-atom row / T-block offsets
 //   k_prep    per-atom Cholesky of T^AA with failure flags, operand forms
 //   k_atom    per-atom products Z_a, W_a (Y_a or X_a)
 //   k_reduce  lower triangles of H and S from the stacked operands
 //   k_mirror  conjugate upper triangles
 // All work is enqueued on one stream; nothing is synchronized inside
-// hs_build_ex.
+// hs_build_ex. The atom-side steps (k_tables, k_prep) do not depend on the
+// k-point and are shared with the resident context (hs_serving.hip).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -18,19 +20,23 @@
 #include "../../include/hs_build.h"
 #include "hs_internal.h"
 
-namespace {
+namespace hs {
 
+namespace {
 thread_local std::string g_last_error;
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+}  // namespace
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+const std::string &last_error() { return g_last_error; }
 
 int hip_fail(hipError_t e, const char *where) {
     g_last_error = std::string(where) + ": " + hipGetErrorString(e);
     return HS_ERR_HIP;
 }
 
-constexpr size_t ALIGN = 256;
-size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
-
-// Device check: the kernels are built for gfx950 only.
+// The kernels are built for gfx950 only.
 int check_device() {
     static std::mutex mu;
     static std::vector<int> ok;   // per device: -1 unknown, 0 no, 1 yes
@@ -48,6 +54,8 @@ int check_device() {
     }
     return ok[dev] ? HS_OK : HS_ERR_UNSUPPORTED;
 }
+
+namespace {
 
 // Atom tables (row and T-block offsets) are written on the device by a small
 // kernel whose inputs travel as kernel arguments, a chunk of up to
@@ -80,49 +88,118 @@ __global__ void __launch_bounds__(256) k_tables(TableChunk c, int *row_off, int 
     }
 }
 
-struct Plan {
-    int n_atoms = 0, n_g = 0, K = 0, max_nl = 0;
-    long long t_total = 0;
-    std::vector<int> tables;   // row_off[N_A+1] then t_off[N_A+1] (host copy)
-    std::vector<unsigned char> nl; // N_L of each atom
-    // workspace carve (byte offsets)
-    size_t o_tables, o_info, o_sel, o_d, o_m1, o_m2, o_z, o_w, total;
+}  // namespace
 
-    // Returns 0, or -8 for an invalid N_L (per-atom entries included).
-    int make(int N_A, const int32_t *nl_per_atom, int N_L, int N_G) {
-        n_atoms = N_A;
-        n_g = N_G;
-        tables.assign(2 * (N_A + 1), 0);
-        nl.assign(N_A, 0);
-        long long rows = 0, tsz = 0;
-        for (int a = 0; a < N_A; ++a) {
-            const int n = nl_per_atom ? nl_per_atom[a] : N_L;
-            if (n < 1 || n > HS_MAX_NL) return -8;
-            nl[a] = (unsigned char)n;
-            tables[a] = (int)rows;
-            tables[N_A + 1 + a] = (int)tsz;
-            rows += n;
-            tsz += (long long)n * n;
-            if (n > max_nl) max_nl = n;
-            if (rows > (1LL << 30) || tsz > (1LL << 30)) return -8;
-        }
-        tables[N_A] = (int)rows;
-        tables[2 * N_A + 1] = (int)tsz;
-        K = (int)rows;
-        t_total = tsz;
-        size_t o = 0;
-        o_tables = o; o = align_up(o + sizeof(int) * tables.size());
-        o_info = o;   o = align_up(o + sizeof(int) * (size_t)N_A);
-        o_sel = o;    o = align_up(o + sizeof(int) * 3 * (size_t)K);
-        o_d = o;      o = align_up(o + sizeof(double) * 2 * (size_t)K);
-        o_m1 = o;     o = align_up(o + 16 * (size_t)t_total);
-        o_m2 = o;     o = align_up(o + 16 * (size_t)t_total);
-        o_z = o;      o = align_up(o + 16 * (size_t)K * (size_t)N_G);
-        o_w = o;      o = align_up(o + 16 * (size_t)K * (size_t)N_G);
-        total = o;
-        return 0;
+int AtomPlan::make(int N_A, const int32_t *nl_per_atom, int N_L) {
+    n_atoms = N_A;
+    row_off.assign(N_A + 1, 0);
+    t_off.assign(N_A + 1, 0);
+    nl.assign(N_A, 0);
+    max_nl = 0;
+    long long rows = 0, tsz = 0;
+    for (int a = 0; a < N_A; ++a) {
+        const int n = nl_per_atom ? nl_per_atom[a] : N_L;
+        if (n < 1 || n > HS_MAX_NL) return -8;
+        nl[a] = (unsigned char)n;
+        row_off[a] = (int)rows;
+        t_off[a] = (int)tsz;
+        rows += n;
+        tsz += (long long)n * n;
+        if (n > max_nl) max_nl = n;
+        if (rows > (1LL << 28) || tsz > (1LL << 30)) return -8;
     }
-};
+    row_off[N_A] = (int)rows;
+    t_off[N_A] = (int)tsz;
+    K = (int)rows;
+    t_total = tsz;
+    return 0;
+}
+
+size_t AtomPlan::atom_bytes() const {
+    size_t o = 0;
+    o = align_up(o + sizeof(int) * 2 * (size_t)(n_atoms + 1));   // tables
+    o = align_up(o + sizeof(int) * (size_t)n_atoms);             // info
+    o = align_up(o + sizeof(int) * 3 * (size_t)K);               // sel
+    o = align_up(o + sizeof(double) * 2 * (size_t)K);            // d
+    o = align_up(o + 16 * (size_t)t_total);                      // M1
+    o = align_up(o + 16 * (size_t)t_total);                      // M2
+    return o;
+}
+
+size_t AtomPlan::kpoint_bytes(int n_g) const {
+    return 2 * align_up(16 * (size_t)K * (size_t)n_g);
+}
+
+void AtomBufs::carve(const AtomPlan &p, char *base) {
+    size_t o = 0;
+    tables = reinterpret_cast<int *>(base + o);
+    o = align_up(o + sizeof(int) * 2 * (size_t)(p.n_atoms + 1));
+    info = reinterpret_cast<int *>(base + o);
+    o = align_up(o + sizeof(int) * (size_t)p.n_atoms);
+    sel = reinterpret_cast<int *>(base + o);
+    o = align_up(o + sizeof(int) * 3 * (size_t)p.K);
+    d = reinterpret_cast<double *>(base + o);
+    o = align_up(o + sizeof(double) * 2 * (size_t)p.K);
+    M1 = reinterpret_cast<double2 *>(base + o);
+    o = align_up(o + 16 * (size_t)p.t_total);
+    M2 = reinterpret_cast<double2 *>(base + o);
+}
+
+Atoms AtomBufs::atoms(const AtomPlan &p) const {
+    Atoms at;
+    at.row_off = tables;
+    at.t_off = tables + p.n_atoms + 1;
+    at.n_atoms = p.n_atoms;
+    at.max_nl = p.max_nl;
+    at.K = p.K;
+    return at;
+}
+
+void KpointBufs::carve(const AtomPlan &p, int n_g, char *base) {
+    const size_t half = align_up(16 * (size_t)p.K * (size_t)n_g);
+    Z = reinterpret_cast<double2 *>(base);
+    W = reinterpret_cast<double2 *>(base + half);
+}
+
+hipError_t enqueue_atoms(const AtomPlan &p, const AtomBufs &ab, const double2 *T_AA,
+                         const double2 *T_BB, const double2 *U, int *info_out, hipStream_t st) {
+    for (int a0 = 0; a0 < p.n_atoms; a0 += TABLE_CHUNK) {
+        TableChunk c;
+        c.n = std::min(TABLE_CHUNK, p.n_atoms - a0);
+        std::memcpy(c.nl, p.nl.data() + a0, c.n);
+        c.a0 = a0;
+        c.row0 = p.row_off[a0];
+        c.t0 = p.t_off[a0];
+        c.last = (a0 + c.n == p.n_atoms);
+        c.n_atoms = p.n_atoms;
+        hipLaunchKernelGGL(k_tables, dim3(1), dim3(256), 0, st, c, ab.tables,
+                           ab.tables + p.n_atoms + 1);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return launch_prep(ab.atoms(p), T_AA, T_BB, U, ab.M1, ab.M2, ab.d, ab.sel,
+                       info_out ? info_out : ab.info, st);
+}
+
+hipError_t enqueue_kpoint(const AtomPlan &p, const AtomBufs &ab, int n_g, const double2 *A,
+                          const double2 *B, const double2 *T_AB, const KpointBufs &kb,
+                          double2 *H, double2 *S, hipStream_t st, const hipEvent_t *ev) {
+    hipError_t e;
+    auto mark = [&](int i) -> hipError_t {
+        return (ev && ev[i]) ? hipEventRecord(ev[i], st) : hipSuccess;
+    };
+    if ((e = mark(1)) != hipSuccess) return e;
+    e = launch_atom(ab.atoms(p), n_g, A, B, T_AB, ab.M1, ab.M2, kb.Z, kb.W, st);
+    if (e != hipSuccess) return e;
+    if ((e = mark(2)) != hipSuccess) return e;
+    e = launch_reduce(p.K, n_g, A, B, kb.Z, kb.W, ab.sel, ab.d, H, S, st, ev ? ev[3] : nullptr);
+    if (e != hipSuccess) return e;
+    return mark(4);
+}
+
+}  // namespace hs
+
+namespace {
 
 int check_args(const hs_complex *A, const hs_complex *B, const hs_complex *T_AA,
                const hs_complex *T_AB, const hs_complex *T_BB, const hs_complex *U, int N_A,
@@ -141,58 +218,27 @@ int check_args(const hs_complex *A, const hs_complex *B, const hs_complex *T_AA,
     return HS_OK;
 }
 
-int run(const Plan &p, const hs_complex *A, const hs_complex *B, const hs_complex *T_AA,
-        const hs_complex *T_AB, const hs_complex *T_BB, const hs_complex *U, hs_complex *H,
-        hs_complex *S, char *ws, int32_t *info_user, hipStream_t st, void **events) {
+const double2 *c2(const hs_complex *x) { return reinterpret_cast<const double2 *>(x); }
+double2 *c2(hs_complex *x) { return reinterpret_cast<double2 *>(x); }
+
+// One-shot build: atom part then k-point part of one workspace.
+int run(const hs::AtomPlan &p, int n_g, const hs_complex *A, const hs_complex *B,
+        const hs_complex *T_AA, const hs_complex *T_AB, const hs_complex *T_BB,
+        const hs_complex *U, hs_complex *H, hs_complex *S, char *ws, int32_t *info_user,
+        hipStream_t st, void **events) {
     hipEvent_t ev[HS_NUM_PHASE_EVENTS] = {};
     if (events)
         for (int i = 0; i < HS_NUM_PHASE_EVENTS; ++i) ev[i] = static_cast<hipEvent_t>(events[i]);
-    auto mark = [&](int i) -> hipError_t {
-        return ev[i] ? hipEventRecord(ev[i], st) : hipSuccess;
-    };
-    int *tables = reinterpret_cast<int *>(ws + p.o_tables);
-    hipError_t e = mark(0);
-    if (e != hipSuccess) return hip_fail(e, "phase event");
-    for (int a0 = 0; a0 < p.n_atoms; a0 += TABLE_CHUNK) {
-        TableChunk c;
-        c.n = std::min(TABLE_CHUNK, p.n_atoms - a0);
-        std::memcpy(c.nl, p.nl.data() + a0, c.n);
-        c.a0 = a0;
-        c.row0 = p.tables[a0];
-        c.t0 = p.tables[p.n_atoms + 1 + a0];
-        c.last = (a0 + c.n == p.n_atoms);
-        c.n_atoms = p.n_atoms;
-        hipLaunchKernelGGL(k_tables, dim3(1), dim3(256), 0, st, c, tables, tables + p.n_atoms + 1);
-        e = hipGetLastError();
-        if (e != hipSuccess) return hip_fail(e, "k_tables launch");
-    }
-
-    hs::Atoms at;
-    at.row_off = tables;
-    at.t_off = tables + p.n_atoms + 1;
-    at.n_atoms = p.n_atoms;
-    at.max_nl = p.max_nl;
-    at.K = p.K;
-    int *info = info_user ? info_user : reinterpret_cast<int *>(ws + p.o_info);
-    int *sel = reinterpret_cast<int *>(ws + p.o_sel);
-    double *d = reinterpret_cast<double *>(ws + p.o_d);
-    double2 *M1 = reinterpret_cast<double2 *>(ws + p.o_m1);
-    double2 *M2 = reinterpret_cast<double2 *>(ws + p.o_m2);
-    double2 *Z = reinterpret_cast<double2 *>(ws + p.o_z);
-    double2 *W = reinterpret_cast<double2 *>(ws + p.o_w);
-    auto c2 = [](const hs_complex *x) { return reinterpret_cast<const double2 *>(x); };
-
-    e = hs::launch_prep(at, c2(T_AA), c2(T_BB), c2(U), M1, M2, d, sel, info, st);
-    if (e != hipSuccess) return hip_fail(e, "k_prep launch");
-    if ((e = mark(1)) != hipSuccess) return hip_fail(e, "phase event");
-    e = hs::launch_atom(at, p.n_g, c2(A), c2(B), c2(T_AB), M1, M2, Z, W, st);
-    if (e != hipSuccess) return hip_fail(e, "k_atom launch");
-    if ((e = mark(2)) != hipSuccess) return hip_fail(e, "phase event");
-    e = hs::launch_reduce(p.K, p.n_g, c2(A), c2(B), Z, W, sel, d,
-                          reinterpret_cast<double2 *>(H), reinterpret_cast<double2 *>(S), st,
-                          ev[3]);
-    if (e != hipSuccess) return hip_fail(e, "k_reduce launch");
-    if ((e = mark(4)) != hipSuccess) return hip_fail(e, "phase event");
+    hipError_t e;
+    if (ev[0] && (e = hipEventRecord(ev[0], st)) != hipSuccess) return hs::hip_fail(e, "phase event");
+    hs::AtomBufs ab;
+    ab.carve(p, ws);
+    hs::KpointBufs kb;
+    kb.carve(p, n_g, ws + p.atom_bytes());
+    e = hs::enqueue_atoms(p, ab, c2(T_AA), c2(T_BB), c2(U), info_user, st);
+    if (e != hipSuccess) return hs::hip_fail(e, "per-atom preparation launch");
+    e = hs::enqueue_kpoint(p, ab, n_g, c2(A), c2(B), c2(T_AB), kb, c2(H), c2(S), st, ev);
+    if (e != hipSuccess) return hs::hip_fail(e, "k-point launch");
     return HS_OK;
 }
 
@@ -202,9 +248,9 @@ extern "C" {
 
 size_t hs_workspace_bytes(int N_A, const int32_t *nl_per_atom, int N_L, int N_G, int mode) {
     if (N_A < 1 || N_G < 1 || mode != HS_FP64) return 0;
-    Plan p;
-    if (p.make(N_A, nl_per_atom, N_L, N_G) != 0) return 0;
-    return p.total;
+    hs::AtomPlan p;
+    if (p.make(N_A, nl_per_atom, N_L) != 0) return 0;
+    return p.atom_bytes() + p.kpoint_bytes(N_G);
 }
 
 int hs_build_ex(const hs_complex *A, const hs_complex *B, const hs_complex *T_AA,
@@ -214,13 +260,14 @@ int hs_build_ex(const hs_complex *A, const hs_complex *B, const hs_complex *T_AA
     int rc = check_args(A, B, T_AA, T_AB, T_BB, U, N_A, N_L, N_G, H, S, opt->nl_per_atom != nullptr);
     if (rc != HS_OK) return rc;
     if (opt->mode != HS_FP64) return -12;
-    Plan p;
-    rc = p.make(N_A, opt->nl_per_atom, N_L, N_G);
+    hs::AtomPlan p;
+    rc = p.make(N_A, opt->nl_per_atom, N_L);
     if (rc != 0) return rc;
-    rc = check_device();
+    rc = hs::check_device();
     if (rc != HS_OK) return rc;
-    if (!opt->workspace || opt->workspace_bytes < p.total) return HS_ERR_WORKSPACE;
-    return run(p, A, B, T_AA, T_AB, T_BB, U, H, S, static_cast<char *>(opt->workspace),
+    if (!opt->workspace || opt->workspace_bytes < p.atom_bytes() + p.kpoint_bytes(N_G))
+        return HS_ERR_WORKSPACE;
+    return run(p, N_G, A, B, T_AA, T_AB, T_BB, U, H, S, static_cast<char *>(opt->workspace),
                opt->info, static_cast<hipStream_t>(opt->stream), opt->phase_events);
 }
 
@@ -229,35 +276,35 @@ int hs_build(const hs_complex *A, const hs_complex *B, const hs_complex *T_AA,
              int N_L, int N_G, hs_complex *H, hs_complex *S) {
     int rc = check_args(A, B, T_AA, T_AB, T_BB, U, N_A, N_L, N_G, H, S, false);
     if (rc != HS_OK) return rc;
-    Plan p;
-    rc = p.make(N_A, nullptr, N_L, N_G);
+    hs::AtomPlan p;
+    rc = p.make(N_A, nullptr, N_L);
     if (rc != 0) return rc;
-    rc = check_device();
+    rc = hs::check_device();
     if (rc != HS_OK) return rc;
     void *ws = nullptr;
-    hipError_t e = hipMalloc(&ws, p.total);
+    hipError_t e = hipMalloc(&ws, p.atom_bytes() + p.kpoint_bytes(N_G));
     if (e == hipErrorOutOfMemory) {
-        g_last_error = "workspace allocation";
+        hs::set_error("workspace allocation");
         return HS_ERR_NOMEM;
     }
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
-    rc = run(p, A, B, T_AA, T_AB, T_BB, U, H, S, static_cast<char *>(ws), nullptr, nullptr,
+    if (e != hipSuccess) return hs::hip_fail(e, "hipMalloc");
+    rc = run(p, N_G, A, B, T_AA, T_AB, T_BB, U, H, S, static_cast<char *>(ws), nullptr, nullptr,
              nullptr);
     e = hipStreamSynchronize(nullptr);
-    if (rc == HS_OK && e != hipSuccess) rc = hip_fail(e, "hs_build execution");
+    if (rc == HS_OK && e != hipSuccess) rc = hs::hip_fail(e, "hs_build execution");
     hipError_t e2 = hipFree(ws);
-    if (rc == HS_OK && e2 != hipSuccess) rc = hip_fail(e2, "hipFree");
+    if (rc == HS_OK && e2 != hipSuccess) rc = hs::hip_fail(e2, "hipFree");
     return rc;
 }
 
 const char *hs_status_string(int status) {
+    const std::string &m = hs::last_error();
     switch (status) {
         case HS_OK: return "success";
-        case HS_ERR_HIP: return g_last_error.empty() ? "HIP runtime error" : g_last_error.c_str();
+        case HS_ERR_HIP: return m.empty() ? "HIP runtime error" : m.c_str();
         case HS_ERR_WORKSPACE: return "workspace too small";
-        case HS_ERR_NOMEM: return "out of device memory";
-        case HS_ERR_UNSUPPORTED:
-            return g_last_error.empty() ? "unsupported size or device" : g_last_error.c_str();
+        case HS_ERR_NOMEM: return m.empty() ? "out of device memory" : m.c_str();
+        case HS_ERR_UNSUPPORTED: return m.empty() ? "unsupported size or device" : m.c_str();
         default:
             if (status < 0) return "invalid argument (-status is its 1-based position)";
             return "unknown status";

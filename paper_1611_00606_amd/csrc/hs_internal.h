@@ -5,6 +5,9 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <string>
+#include <vector>
+
 namespace hs {
 
 // Device-side description of the atoms of one build.
@@ -45,5 +48,56 @@ hipError_t launch_reduce(int K, int n_g, const double2 *A, const double2 *B,
                          const double2 *Z, const double2 *W, const int *sel,
                          const double *d, double2 *H, double2 *S, hipStream_t st,
                          hipEvent_t mid_event);
+
+// Error bookkeeping shared by the C entry points (thread-local message).
+void set_error(const std::string &msg);
+const std::string &last_error();
+int hip_fail(hipError_t e, const char *where);   // records the message, returns HS_ERR_HIP
+int check_device();                              // HS_OK on gfx950, else an error status
+
+// ---------------------------------------------------------------------------
+// Host-side plan of one atom set and the enqueue steps shared by the one-shot
+// build (hs_build_ex) and the resident context (hs_ctx).
+
+// Atom-side sizes and offsets (host copy).
+struct AtomPlan {
+    int n_atoms = 0, K = 0, max_nl = 0;
+    long long t_total = 0;
+    std::vector<int> row_off, t_off;      // [N_A+1] each
+    std::vector<unsigned char> nl;        // [N_A]
+    // Returns 0, or -8 for an invalid N_L (per-atom entries included).
+    int make(int N_A, const int32_t *nl_per_atom, int N_L);
+    // Device bytes of the k-independent buffers (AtomBufs).
+    size_t atom_bytes() const;
+    // Device bytes of the per-k-point buffers (Z, W) for N_G.
+    size_t kpoint_bytes(int n_g) const;
+};
+
+// k-independent device buffers of an atom set, carved from one allocation.
+struct AtomBufs {
+    int *tables;      // row_off [N_A+1], then t_off [N_A+1]
+    int *info;        // [N_A]
+    int *sel;         // [3K]
+    double *d;        // [2K]
+    double2 *M1;      // [t_total]
+    double2 *M2;      // [t_total]
+    void carve(const AtomPlan &p, char *base);
+    Atoms atoms(const AtomPlan &p) const;
+};
+
+// Per-k-point device buffers.
+struct KpointBufs {
+    double2 *Z, *W;   // [K][N_G] each
+    void carve(const AtomPlan &p, int n_g, char *base);
+};
+
+// Tables, per-atom Cholesky and operand preparation (k-independent).
+hipError_t enqueue_atoms(const AtomPlan &p, const AtomBufs &ab, const double2 *T_AA,
+                         const double2 *T_BB, const double2 *U, int *info_out, hipStream_t st);
+// Per-atom products and the reductions for one k-point. ev: optional phase
+// events [1..4] as in hs_options.phase_events (ev[0] is recorded by the caller).
+hipError_t enqueue_kpoint(const AtomPlan &p, const AtomBufs &ab, int n_g, const double2 *A,
+                          const double2 *B, const double2 *T_AB, const KpointBufs &kb,
+                          double2 *H, double2 *S, hipStream_t st, const hipEvent_t *ev);
 
 }  // namespace hs

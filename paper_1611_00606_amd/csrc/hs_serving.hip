@@ -1,0 +1,420 @@
+// Resident context (hs_ctx) and the continuous-batching serving loop
+// (hs_server) for many k-points of one atom set.
+//
+// The context keeps the k-independent part of Alg. 1 on the device: the
+// per-atom Cholesky factors / failure flags and operand forms (M1, M2), the
+// per-row metadata of the reductions, and a copy of T^AB. One k-point then
+// costs the per-atom products and the two reductions only.
+//
+// The server owns one device arena and n_slots HIP streams (default
+// priority). Requests are admitted in arrival order when a slot is free and
+// their footprint fits in the arena (first fit over a free list); each
+// admitted request copies its A, B (2-D copies from the caller's host rows),
+// builds on its slot's stream, and a host callback on that stream stamps the
+// completion time. Results stay in the arena until released.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <chrono>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/hs_build.h"
+#include "hs_internal.h"
+
+struct hs_ctx {
+    hs::AtomPlan plan;
+    char *mem = nullptr;          // atom buffers, then the T^AB copy
+    hs::AtomBufs ab;
+    double2 *T_AB = nullptr;
+    int device = 0;
+};
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+size_t footprint(const hs::AtomPlan &p, int n_g) {
+    const size_t ab = align_up(16 * (size_t)p.K * (size_t)n_g);
+    const size_t hs = align_up(16 * (size_t)n_g * (size_t)n_g);
+    return 2 * ab + 2 * hs + p.kpoint_bytes(n_g);
+}
+
+}  // namespace
+
+extern "C" {
+
+int hs_ctx_create(const hs_complex *T_AA, const hs_complex *T_AB, const hs_complex *T_BB,
+                  const hs_complex *U, int N_A, int N_L, const int32_t *nl_per_atom,
+                  void *stream, hs_ctx **out) {
+    if (!T_AA) return -1;
+    if (!T_AB) return -2;
+    if (!T_BB) return -3;
+    if (!U) return -4;
+    if (N_A < 1) return -5;
+    if (!nl_per_atom && (N_L < 1 || N_L > HS_MAX_NL)) return -6;
+    if (!out) return -9;
+    *out = nullptr;
+    std::unique_ptr<hs_ctx> c(new hs_ctx);
+    if (c->plan.make(N_A, nl_per_atom, N_L) != 0) return nl_per_atom ? -7 : -6;
+    int rc = hs::check_device();
+    if (rc != HS_OK) return rc;
+    hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) return hs::hip_fail(e, "hipGetDevice");
+    const size_t abytes = c->plan.atom_bytes();
+    const size_t tbytes = 16 * (size_t)c->plan.t_total;
+    e = hipMalloc(&c->mem, abytes + tbytes);
+    if (e == hipErrorOutOfMemory) {
+        hs::set_error("context allocation");
+        return HS_ERR_NOMEM;
+    }
+    if (e != hipSuccess) return hs::hip_fail(e, "hipMalloc");
+    c->ab.carve(c->plan, c->mem);
+    c->T_AB = reinterpret_cast<double2 *>(c->mem + abytes);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    e = hipMemcpyAsync(c->T_AB, T_AB, tbytes, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess)
+        e = hs::enqueue_atoms(c->plan, c->ab, reinterpret_cast<const double2 *>(T_AA),
+                              reinterpret_cast<const double2 *>(T_BB),
+                              reinterpret_cast<const double2 *>(U), nullptr, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        (void)hipFree(c->mem);
+        return hs::hip_fail(e, "context preparation");
+    }
+    *out = c.release();
+    return HS_OK;
+}
+
+int hs_ctx_rows(const hs_ctx *ctx) { return ctx ? ctx->plan.K : 0; }
+
+int hs_ctx_info(const hs_ctx *ctx, int32_t *info_host) {
+    if (!ctx) return -1;
+    if (!info_host) return -2;
+    hipError_t e = hipMemcpy(info_host, ctx->ab.info, sizeof(int32_t) * ctx->plan.n_atoms,
+                             hipMemcpyDeviceToHost);
+    return e == hipSuccess ? HS_OK : hs::hip_fail(e, "hs_ctx_info");
+}
+
+size_t hs_ctx_workspace_bytes(const hs_ctx *ctx, int N_G, int mode) {
+    if (!ctx || N_G < 1 || mode != HS_FP64) return 0;
+    return ctx->plan.kpoint_bytes(N_G);
+}
+
+size_t hs_ctx_footprint_bytes(const hs_ctx *ctx, int N_G, int mode) {
+    if (!ctx || N_G < 1 || mode != HS_FP64) return 0;
+    return footprint(ctx->plan, N_G);
+}
+
+int hs_ctx_build(const hs_ctx *ctx, const hs_complex *A, const hs_complex *B, int N_G,
+                 hs_complex *H, hs_complex *S, const hs_options *opt) {
+    if (!ctx) return -1;
+    if (!A) return -2;
+    if (!B) return -3;
+    if (N_G < 1) return -4;
+    if (!H) return -5;
+    if (!S) return -6;
+    if (!opt || opt->mode != HS_FP64) return -7;
+    if (!opt->workspace || opt->workspace_bytes < ctx->plan.kpoint_bytes(N_G))
+        return HS_ERR_WORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(opt->stream);
+    hipEvent_t ev[HS_NUM_PHASE_EVENTS] = {};
+    if (opt->phase_events)
+        for (int i = 0; i < HS_NUM_PHASE_EVENTS; ++i)
+            ev[i] = static_cast<hipEvent_t>(opt->phase_events[i]);
+    hipError_t e;
+    if (ev[0] && (e = hipEventRecord(ev[0], st)) != hipSuccess) return hs::hip_fail(e, "phase event");
+    hs::KpointBufs kb;
+    kb.carve(ctx->plan, N_G, static_cast<char *>(opt->workspace));
+    e = hs::enqueue_kpoint(ctx->plan, ctx->ab, N_G, reinterpret_cast<const double2 *>(A),
+                           reinterpret_cast<const double2 *>(B), ctx->T_AB, kb,
+                           reinterpret_cast<double2 *>(H), reinterpret_cast<double2 *>(S), st, ev);
+    return e == hipSuccess ? HS_OK : hs::hip_fail(e, "hs_ctx_build launch");
+}
+
+void hs_ctx_destroy(hs_ctx *ctx) {
+    if (!ctx) return;
+    if (ctx->mem) (void)hipFree(ctx->mem);
+    delete ctx;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Server
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+// First-fit allocator over [0, size) with coalescing free list.
+class Arena {
+   public:
+    void init(size_t size) {
+        free_.clear();
+        free_[0] = size;
+        used_ = 0;
+    }
+    bool alloc(size_t n, size_t &off) {
+        n = align_up(n);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                off = it->first;
+                const size_t rest = it->second - n;
+                free_.erase(it);
+                if (rest) free_[off + n] = rest;
+                used_ += n;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t n) {
+        n = align_up(n);
+        used_ -= n;
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t used() const { return used_; }
+
+   private:
+    std::map<size_t, size_t> free_;
+    size_t used_ = 0;
+};
+
+struct Live {
+    hs_request req;
+    size_t off = 0, bytes = 0;
+    int slot = -1;
+    int status = 0;
+    double t_submit = 0, t_admit = 0;
+    std::atomic<double> t_done{0.0};
+    std::atomic<int> done{0};
+    Clock::time_point epoch;
+};
+
+void on_done(void *p) {
+    Live *l = static_cast<Live *>(p);
+    l->t_done.store(std::chrono::duration<double>(Clock::now() - l->epoch).count());
+    l->done.store(1, std::memory_order_release);
+}
+
+}  // namespace
+
+struct hs_server {
+    hs_ctx *ctx = nullptr;
+    int mode = HS_FP64;
+    char *arena_mem = nullptr;
+    size_t arena_bytes = 0;
+    Arena arena;
+    std::vector<hipStream_t> streams;
+    std::vector<Live *> slot_req;              // request running on each slot
+    std::deque<Live *> queue;                  // submitted, not admitted
+    std::deque<Live *> done;                   // completed, not popped
+    std::unordered_map<int64_t, Live *> popped;  // popped, not released
+    Clock::time_point epoch;
+    double now() const { return std::chrono::duration<double>(Clock::now() - epoch).count(); }
+};
+
+namespace {
+
+// Launch one admitted request on its slot; returns a status.
+int launch(hs_server *s, Live *l) {
+    const hs::AtomPlan &p = s->ctx->plan;
+    const int n_g = l->req.N_G;
+    char *base = s->arena_mem + l->off;
+    const size_t ab = align_up(16 * (size_t)p.K * (size_t)n_g);
+    const size_t hsz = align_up(16 * (size_t)n_g * (size_t)n_g);
+    hs_complex *A = reinterpret_cast<hs_complex *>(base);
+    hs_complex *B = reinterpret_cast<hs_complex *>(base + ab);
+    hs_complex *H = reinterpret_cast<hs_complex *>(base + 2 * ab);
+    hs_complex *S = reinterpret_cast<hs_complex *>(base + 2 * ab + hsz);
+    char *ws = base + 2 * ab + 2 * hsz;
+    hipStream_t st = s->streams[l->slot];
+    const size_t row = 16 * (size_t)n_g, pitch = 16 * (size_t)l->req.ld;
+    hipError_t e = hipMemcpy2DAsync(A, row, l->req.A_host, pitch, row, p.K, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpy2DAsync(B, row, l->req.B_host, pitch, row, p.K, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hs::hip_fail(e, "request input copy");
+    hs_options opt;
+    std::memset(&opt, 0, sizeof(opt));
+    opt.stream = st;
+    opt.workspace = ws;
+    opt.workspace_bytes = p.kpoint_bytes(n_g);
+    opt.mode = s->mode;
+    int rc = hs_ctx_build(s->ctx, A, B, n_g, H, S, &opt);
+    if (rc != HS_OK) return rc;
+    e = hipLaunchHostFunc(st, on_done, l);
+    if (e != hipSuccess) return hs::hip_fail(e, "completion callback");
+    return HS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hs_server_create(hs_ctx *ctx, int n_slots, size_t arena_bytes, int mode, hs_server **out) {
+    if (!ctx) return -1;
+    if (n_slots < 1 || n_slots > 64) return -2;
+    if (arena_bytes == 0) return -3;
+    if (mode != HS_FP64) return -4;
+    if (!out) return -5;
+    *out = nullptr;
+    std::unique_ptr<hs_server> s(new hs_server);
+    s->ctx = ctx;
+    s->mode = mode;
+    s->arena_bytes = arena_bytes;
+    hipError_t e = hipMalloc(&s->arena_mem, arena_bytes);
+    if (e == hipErrorOutOfMemory) {
+        hs::set_error("server arena allocation");
+        return HS_ERR_NOMEM;
+    }
+    if (e != hipSuccess) return hs::hip_fail(e, "hipMalloc");
+    s->arena.init(arena_bytes);
+    s->streams.resize(n_slots, nullptr);
+    s->slot_req.assign(n_slots, nullptr);
+    for (int i = 0; i < n_slots; ++i) {
+        e = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            for (int j = 0; j < i; ++j) (void)hipStreamDestroy(s->streams[j]);
+            (void)hipFree(s->arena_mem);
+            return hs::hip_fail(e, "hipStreamCreateWithFlags");
+        }
+    }
+    s->epoch = Clock::now();
+    *out = s.release();
+    return HS_OK;
+}
+
+int hs_server_submit(hs_server *s, const hs_request *req) {
+    if (!s) return -1;
+    if (!req || req->N_G < 1 || !req->A_host || !req->B_host || req->ld < req->N_G) return -2;
+    if (footprint(s->ctx->plan, req->N_G) > s->arena_bytes) {
+        hs::set_error("request footprint exceeds the server arena");
+        return HS_ERR_NOMEM;
+    }
+    Live *l = new Live;
+    l->req = *req;
+    l->bytes = footprint(s->ctx->plan, req->N_G);
+    l->epoch = s->epoch;
+    l->t_submit = s->now();
+    s->queue.push_back(l);
+    return HS_OK;
+}
+
+int hs_server_progress(hs_server *s) {
+    if (!s) return -1;
+    // completions
+    for (size_t i = 0; i < s->slot_req.size(); ++i) {
+        Live *l = s->slot_req[i];
+        if (l && l->done.load(std::memory_order_acquire)) {
+            s->slot_req[i] = nullptr;
+            s->done.push_back(l);
+        }
+    }
+    // admissions, in arrival order
+    while (!s->queue.empty()) {
+        int slot = -1;
+        for (size_t i = 0; i < s->slot_req.size(); ++i)
+            if (!s->slot_req[i]) {
+                slot = (int)i;
+                break;
+            }
+        if (slot < 0) break;
+        Live *l = s->queue.front();
+        size_t off;
+        if (!s->arena.alloc(l->bytes, off)) break;
+        s->queue.pop_front();
+        l->off = off;
+        l->slot = slot;
+        l->t_admit = s->now();
+        s->slot_req[slot] = l;
+        const int rc = launch(s, l);
+        if (rc != HS_OK) {
+            // nothing more will complete on this request: drain what was
+            // enqueued for it (so its arena space is idle) and report it now
+            (void)hipStreamSynchronize(s->streams[slot]);
+            s->slot_req[slot] = nullptr;
+            l->status = rc;
+            l->t_done.store(s->now());
+            s->done.push_back(l);
+        }
+    }
+    return (int)s->done.size();
+}
+
+int hs_server_pop(hs_server *s, hs_result *out) {
+    if (!s || !out) return -1;
+    if (s->done.empty()) return 0;
+    Live *l = s->done.front();
+    s->done.pop_front();
+    const hs::AtomPlan &p = s->ctx->plan;
+    const int n_g = l->req.N_G;
+    char *base = s->arena_mem + l->off;
+    const size_t ab = align_up(16 * (size_t)p.K * (size_t)n_g);
+    const size_t hsz = align_up(16 * (size_t)n_g * (size_t)n_g);
+    out->id = l->req.id;
+    out->N_G = n_g;
+    out->status = l->status;
+    out->H = reinterpret_cast<hs_complex *>(base + 2 * ab);
+    out->S = reinterpret_cast<hs_complex *>(base + 2 * ab + hsz);
+    out->t_submit = l->t_submit;
+    out->t_admit = l->t_admit;
+    out->t_done = l->t_done.load();
+    s->popped[l->req.id] = l;
+    return 1;
+}
+
+int hs_server_release(hs_server *s, int64_t id) {
+    if (!s) return -1;
+    auto it = s->popped.find(id);
+    if (it == s->popped.end()) return -2;
+    Live *l = it->second;
+    s->popped.erase(it);
+    if (l->slot >= 0) s->arena.release(l->off, l->bytes);
+    delete l;
+    return HS_OK;
+}
+
+int hs_server_pending(const hs_server *s) {
+    if (!s) return 0;
+    int n = (int)s->queue.size() + (int)s->done.size();
+    for (Live *l : s->slot_req) n += l != nullptr;
+    return n;
+}
+
+size_t hs_server_used_bytes(const hs_server *s) { return s ? s->arena.used() : 0; }
+
+double hs_server_now(const hs_server *s) { return s ? s->now() : 0.0; }
+
+void hs_server_destroy(hs_server *s) {
+    if (!s) return;
+    for (hipStream_t st : s->streams) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
+    for (Live *l : s->slot_req) delete l;
+    for (Live *l : s->queue) delete l;
+    for (Live *l : s->done) delete l;
+    for (auto &kv : s->popped) delete kv.second;
+    if (s->arena_mem) (void)hipFree(s->arena_mem);
+    delete s;
+}
+
+}  // extern "C"

@@ -109,3 +109,33 @@ def test_binding_rejects_host_tensors():
     t = torch.zeros(4, dtype=torch.complex128)
     with pytest.raises(ValueError):
         P.hs_build(t, t, t, t, t, t, 1, 2, 2, t, t)
+
+
+def test_context_and_server_argument_checks():
+    lib = P.load_library()
+    out = ctypes.c_void_p()
+    assert lib.hs_ctx_create(None, FAKE, FAKE, FAKE, 2, 4, None, None, ctypes.byref(out)) == -1
+    assert lib.hs_ctx_create(FAKE, FAKE, FAKE, None, 2, 4, None, None, ctypes.byref(out)) == -4
+    assert lib.hs_ctx_create(FAKE, FAKE, FAKE, FAKE, 0, 4, None, None, ctypes.byref(out)) == -5
+    assert lib.hs_ctx_create(FAKE, FAKE, FAKE, FAKE, 2, 200, None, None, ctypes.byref(out)) == -6
+    nl = np.array([4, 0], np.int32)
+    assert lib.hs_ctx_create(FAKE, FAKE, FAKE, FAKE, 2, 0,
+                             nl.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), None,
+                             ctypes.byref(out)) == -7
+    assert lib.hs_ctx_create(FAKE, FAKE, FAKE, FAKE, 2, 4, None, None, None) == -9
+    assert lib.hs_ctx_rows(None) == 0
+    assert lib.hs_ctx_workspace_bytes(None, 10, 0) == 0
+    assert lib.hs_ctx_footprint_bytes(None, 10, 0) == 0
+    opt = Bd.hs_options()
+    assert lib.hs_ctx_build(None, FAKE, FAKE, 8, FAKE, FAKE, ctypes.byref(opt)) == -1
+    assert lib.hs_server_create(None, 2, 1 << 20, 0, ctypes.byref(out)) == -1
+    assert lib.hs_server_create(FAKE, 0, 1 << 20, 0, ctypes.byref(out)) == -2
+    assert lib.hs_server_create(FAKE, 2, 0, 0, ctypes.byref(out)) == -3
+    assert lib.hs_server_create(FAKE, 2, 1 << 20, 9, ctypes.byref(out)) == -4
+    assert lib.hs_server_submit(None, None) == -1
+    assert lib.hs_server_progress(None) == -1
+    assert lib.hs_server_pop(None, None) == -1
+    assert lib.hs_server_release(None, 3) == -1
+    assert lib.hs_server_pending(None) == 0
+    assert lib.hs_server_used_bytes(None) == 0
+    assert lib.hs_server_now(None) == 0.0
