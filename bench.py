@@ -122,8 +122,62 @@ def cpu_baseline(p, seconds: float):
     }
 
 
+def timed_builds(run, steps: int, warmup: int, hip):
+    """Mean per-phase and whole-build milliseconds of `steps` builds."""
+    import torch
+    from paper_1611_00606_amd import HS_NUM_PHASE_EVENTS
+    for _ in range(warmup):
+        run.run()
+    torch.cuda.synchronize()
+    evs = [hip.create(HS_NUM_PHASE_EVENTS) for _ in range(steps)]
+    for k in range(steps):
+        run.run(phase_events=evs[k])
+    torch.cuda.synchronize()
+    ph = np.array([[hip.elapsed_ms(e[i], e[i + 1]) for i in range(HS_NUM_PHASE_EVENTS - 1)]
+                   for e in evs]).mean(axis=0)
+    total = float(np.mean([hip.elapsed_ms(e[0], e[-1]) for e in evs]))
+    hip.destroy([e for es in evs for e in es])
+    return ph, total
+
+
+def split_bench(p, steps: int, warmup: int, fp64_ms: float, hip, n_cols: int = 12):
+    """Split-precision form on the same workload: time, speedup over the FP64
+    path, and relative Frobenius error of H and of S against the CPU oracle
+    on sampled columns."""
+    import torch
+    import oracle
+    from paper_1611_00606_amd import HS_SPLIT_F16, DeviceBuild
+    from paper_1611_00606_amd.flops import algorithmic_flops
+
+    run = DeviceBuild.from_problem(p, device="cuda:0", mode=HS_SPLIT_F16)
+    ph, total = timed_builds(run, steps, warmup, hip)
+    info = run.info.cpu().numpy()
+    rng = np.random.default_rng(1234)
+    cols = np.sort(rng.choice(p.N_G, size=min(n_cols, p.N_G), replace=False))
+    idx = torch.as_tensor(cols, device=run.H.device)
+    Hc = run.H.index_select(1, idx).cpu().numpy()
+    Sc = run.S.index_select(1, idx).cpu().numpy()
+    del run
+    torch.cuda.empty_cache()
+    Hr = oracle.hamiltonian_columns(p.A, p.B, p.T_AA, p.T_AB, p.T_BB, p.nl, cols)
+    Sr = oracle.overlap_columns(p.A, p.B, p.U, p.nl, cols)
+    f = algorithmic_flops(p.nl, p.N_G, info)
+    return {
+        "mode": "split_f16 (4 x 8-bit slices, FP16 MFMA, exact FP32 accumulation, FP64 recombination)",
+        "ms_per_step": round(total, 3),
+        "value": round(f / (total * 1e-3) / 1e12, 3),
+        "unit": "TFLOP/s (FP64-equivalent)",
+        "speedup_vs_fp64": round(fp64_ms / total, 3),
+        "phases_ms": {"prep_cholesky": round(float(ph[0]), 4), "atom_products": round(float(ph[1]), 4),
+                      "slice_and_reduce_HS": round(float(ph[2]), 4), "mirror": round(float(ph[3]), 4)},
+        "rel_err_H": float(np.linalg.norm(Hc - Hr) / np.linalg.norm(Hr)),
+        "rel_err_S": float(np.linalg.norm(Sc - Sr) / np.linalg.norm(Sr)),
+        "err_sample": f"{len(cols)} seeded columns of H and S vs the CPU oracle",
+    }
+
+
 def serving_bench(seed: int, n_slots: int = 4, arena_gb: float = 24.0, n_sets: int = 4,
-                  load: float = 0.8, streams: int = 3):
+                  load: float = 0.8, streams: int = 3, mode: int = 0):
     """Serving form: 64 k-point requests on one resident atom set (64 atoms,
     N_L = 64), N_G integer-uniform in [1500, 9000], Poisson arrivals at
     `load` / (mean latency of a request served alone), continuous batching
@@ -155,7 +209,7 @@ def serving_bench(seed: int, n_slots: int = 4, arena_gb: float = 24.0, n_sets: i
     reqs = [{"id": r, "N_G": n, "A_ptr": pool[r % n_sets][0].data_ptr(),
              "B_ptr": pool[r % n_sets][1].data_ptr(), "ld": ng_max} for r, n in enumerate(sizes)]
     arena = int(arena_gb * 1e9)
-    loop = ServingLoop(ctx, n_slots, arena)
+    loop = ServingLoop(ctx, n_slots, arena, mode=mode)
     # calibration: a spread of requests served one at a time
     cal_ids = [int(i) for i in np.argsort(sizes)[np.linspace(0, len(sizes) - 1, 8).astype(int)]]
     alone = []
@@ -184,7 +238,7 @@ def serving_bench(seed: int, n_slots: int = 4, arena_gb: float = 24.0, n_sets: i
     out["latency_samples"] = len(reqs) * streams
     out["offered_rate_per_s"] = [round(x, 3) for x in offered]
     out.update({
-        "mode": "fp64",
+        "mode": "split_f16" if mode else "fp64",
         "workload": "64 requests, N_A=64 atoms, N_L=64, N_G uniform in [1500, 9000], Poisson arrivals",
         "arrival_rate_per_s": rate,   # nominal Poisson rate; offered_rate_per_s is realized
         "load": load,
@@ -208,6 +262,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving-form measurement (k-point builds/s, p50/p99)")
+    ap.add_argument("--no-split", action="store_true",
+                    help="skip the split-precision measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run one plain device copy of MIB MiB (to scale HBM byte "
                          "counters against a kernel of known traffic) and exit")
@@ -313,11 +369,17 @@ def main():
     }
     del run
     torch.cuda.empty_cache()
+    if not args.no_split:
+        print("bench: split precision", file=sys.stderr, flush=True)
+        hip = HipEvents()
+        out["split"] = split_bench(p, max(3, args.steps // 2), 1, ms_step, hip)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
     if not args.no_serving:
         print("bench: serving stream", file=sys.stderr, flush=True)
         out["serving"] = serving_bench(args.seed)
+        if not args.no_split:
+            out["serving_split"] = serving_bench(args.seed, mode=1)
     print(json.dumps(out), flush=True)
 
 

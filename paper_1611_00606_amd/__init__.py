@@ -13,6 +13,7 @@ from ._binding import (  # noqa: F401
     HS_ERR_NOMEM,
     HS_ERR_UNSUPPORTED,
     HS_FP64,
+    HS_SPLIT_F16,
     HS_MAX_NL,
     HS_NUM_PHASE_EVENTS,
     HSError,

@@ -126,8 +126,11 @@ size_t AtomPlan::atom_bytes() const {
     return o;
 }
 
-size_t AtomPlan::kpoint_bytes(int n_g) const {
-    return 2 * align_up(16 * (size_t)K * (size_t)n_g);
+size_t AtomPlan::kpoint_bytes(int n_g, int mode) const {
+    size_t b = 2 * align_up(16 * (size_t)K * (size_t)n_g);
+    if (mode == HS_SPLIT_F16)
+        b += NSPLIT * (align_up(split_slice_bytes(K, n_g)) + align_up(8 * (size_t)n_g));
+    return b;
 }
 
 void AtomBufs::carve(const AtomPlan &p, char *base) {
@@ -155,10 +158,20 @@ Atoms AtomBufs::atoms(const AtomPlan &p) const {
     return at;
 }
 
-void KpointBufs::carve(const AtomPlan &p, int n_g, char *base) {
+void KpointBufs::carve(const AtomPlan &p, int n_g, int mode, char *base) {
     const size_t half = align_up(16 * (size_t)p.K * (size_t)n_g);
     Z = reinterpret_cast<double2 *>(base);
     W = reinterpret_cast<double2 *>(base + half);
+    size_t o = 2 * half;
+    for (int i = 0; i < NSPLIT; ++i) {
+        sl[i] = nullptr;
+        mx[i] = nullptr;
+        if (mode != HS_SPLIT_F16) continue;
+        sl[i] = reinterpret_cast<_Float16 *>(base + o);
+        o += align_up(split_slice_bytes(p.K, n_g));
+        mx[i] = reinterpret_cast<unsigned long long *>(base + o);
+        o += align_up(8 * (size_t)n_g);
+    }
 }
 
 hipError_t enqueue_atoms(const AtomPlan &p, const AtomBufs &ab, const double2 *T_AA,
@@ -181,9 +194,10 @@ hipError_t enqueue_atoms(const AtomPlan &p, const AtomBufs &ab, const double2 *T
                        info_out ? info_out : ab.info, st);
 }
 
-hipError_t enqueue_kpoint(const AtomPlan &p, const AtomBufs &ab, int n_g, const double2 *A,
-                          const double2 *B, const double2 *T_AB, const KpointBufs &kb,
-                          double2 *H, double2 *S, hipStream_t st, const hipEvent_t *ev) {
+hipError_t enqueue_kpoint(const AtomPlan &p, const AtomBufs &ab, int n_g, int mode,
+                          const double2 *A, const double2 *B, const double2 *T_AB,
+                          const KpointBufs &kb, double2 *H, double2 *S, hipStream_t st,
+                          const hipEvent_t *ev) {
     hipError_t e;
     auto mark = [&](int i) -> hipError_t {
         return (ev && ev[i]) ? hipEventRecord(ev[i], st) : hipSuccess;
@@ -192,8 +206,30 @@ hipError_t enqueue_kpoint(const AtomPlan &p, const AtomBufs &ab, int n_g, const 
     e = launch_atom(ab.atoms(p), n_g, A, B, T_AB, ab.M1, ab.M2, kb.Z, kb.W, st);
     if (e != hipSuccess) return e;
     if ((e = mark(2)) != hipSuccess) return e;
-    e = launch_reduce(p.K, n_g, A, B, kb.Z, kb.W, ab.sel, ab.d, H, S, st, ev ? ev[3] : nullptr);
+    if (mode == HS_SPLIT_F16) {
+        // operands: 0 A, 1 U B, 2 Z, 3 B, 4 P3 (W, or A on failure-branch rows), 5 W
+        const int K = p.K;
+        const SliceSrc src[NSPLIT] = {
+            {A, nullptr, nullptr, nullptr, kb.mx[0], kb.sl[0]},
+            {B, nullptr, nullptr, ab.d + K, kb.mx[1], kb.sl[1]},
+            {kb.Z, nullptr, nullptr, nullptr, kb.mx[2], kb.sl[2]},
+            {B, nullptr, nullptr, nullptr, kb.mx[3], kb.sl[3]},
+            {kb.W, A, ab.sel + 2 * (size_t)K, nullptr, kb.mx[4], kb.sl[4]},
+            {kb.W, nullptr, nullptr, nullptr, kb.mx[5], kb.sl[5]},
+        };
+        for (int i = 0; i < NSPLIT; ++i)
+            if ((e = launch_slice(src[i], K, n_g, st)) != hipSuccess) return e;
+        SliceView v[NSPLIT];
+        for (int i = 0; i < NSPLIT; ++i) v[i] = SliceView{kb.sl[i], kb.mx[i]};
+        const SliceView hseg[3][2] = {{v[2], v[3]}, {v[3], v[2]}, {v[4], v[5]}};
+        const SliceView sseg[2][2] = {{v[0], v[0]}, {v[1], v[1]}};
+        e = launch_split_reduce(K, n_g, hseg, sseg, H, S, st);
+    } else {
+        e = launch_reduce(p.K, n_g, A, B, kb.Z, kb.W, ab.sel, ab.d, H, S, st);
+    }
     if (e != hipSuccess) return e;
+    if ((e = mark(3)) != hipSuccess) return e;
+    if ((e = launch_mirror(H, S, n_g, st)) != hipSuccess) return e;
     return mark(4);
 }
 
@@ -222,7 +258,7 @@ const double2 *c2(const hs_complex *x) { return reinterpret_cast<const double2 *
 double2 *c2(hs_complex *x) { return reinterpret_cast<double2 *>(x); }
 
 // One-shot build: atom part then k-point part of one workspace.
-int run(const hs::AtomPlan &p, int n_g, const hs_complex *A, const hs_complex *B,
+int run(const hs::AtomPlan &p, int n_g, int mode, const hs_complex *A, const hs_complex *B,
         const hs_complex *T_AA, const hs_complex *T_AB, const hs_complex *T_BB,
         const hs_complex *U, hs_complex *H, hs_complex *S, char *ws, int32_t *info_user,
         hipStream_t st, void **events) {
@@ -234,10 +270,10 @@ int run(const hs::AtomPlan &p, int n_g, const hs_complex *A, const hs_complex *B
     hs::AtomBufs ab;
     ab.carve(p, ws);
     hs::KpointBufs kb;
-    kb.carve(p, n_g, ws + p.atom_bytes());
+    kb.carve(p, n_g, mode, ws + p.atom_bytes());
     e = hs::enqueue_atoms(p, ab, c2(T_AA), c2(T_BB), c2(U), info_user, st);
     if (e != hipSuccess) return hs::hip_fail(e, "per-atom preparation launch");
-    e = hs::enqueue_kpoint(p, ab, n_g, c2(A), c2(B), c2(T_AB), kb, c2(H), c2(S), st, ev);
+    e = hs::enqueue_kpoint(p, ab, n_g, mode, c2(A), c2(B), c2(T_AB), kb, c2(H), c2(S), st, ev);
     if (e != hipSuccess) return hs::hip_fail(e, "k-point launch");
     return HS_OK;
 }
@@ -247,10 +283,10 @@ int run(const hs::AtomPlan &p, int n_g, const hs_complex *A, const hs_complex *B
 extern "C" {
 
 size_t hs_workspace_bytes(int N_A, const int32_t *nl_per_atom, int N_L, int N_G, int mode) {
-    if (N_A < 1 || N_G < 1 || mode != HS_FP64) return 0;
+    if (N_A < 1 || N_G < 1 || !hs::valid_mode(mode)) return 0;
     hs::AtomPlan p;
     if (p.make(N_A, nl_per_atom, N_L) != 0) return 0;
-    return p.atom_bytes() + p.kpoint_bytes(N_G);
+    return p.atom_bytes() + p.kpoint_bytes(N_G, mode);
 }
 
 int hs_build_ex(const hs_complex *A, const hs_complex *B, const hs_complex *T_AA,
@@ -259,15 +295,15 @@ int hs_build_ex(const hs_complex *A, const hs_complex *B, const hs_complex *T_AA
     if (!opt) return -12;
     int rc = check_args(A, B, T_AA, T_AB, T_BB, U, N_A, N_L, N_G, H, S, opt->nl_per_atom != nullptr);
     if (rc != HS_OK) return rc;
-    if (opt->mode != HS_FP64) return -12;
+    if (!hs::valid_mode(opt->mode)) return -12;
     hs::AtomPlan p;
     rc = p.make(N_A, opt->nl_per_atom, N_L);
     if (rc != 0) return rc;
     rc = hs::check_device();
     if (rc != HS_OK) return rc;
-    if (!opt->workspace || opt->workspace_bytes < p.atom_bytes() + p.kpoint_bytes(N_G))
+    if (!opt->workspace || opt->workspace_bytes < p.atom_bytes() + p.kpoint_bytes(N_G, opt->mode))
         return HS_ERR_WORKSPACE;
-    return run(p, N_G, A, B, T_AA, T_AB, T_BB, U, H, S, static_cast<char *>(opt->workspace),
+    return run(p, N_G, opt->mode, A, B, T_AA, T_AB, T_BB, U, H, S, static_cast<char *>(opt->workspace),
                opt->info, static_cast<hipStream_t>(opt->stream), opt->phase_events);
 }
 
@@ -288,8 +324,8 @@ int hs_build(const hs_complex *A, const hs_complex *B, const hs_complex *T_AA,
         return HS_ERR_NOMEM;
     }
     if (e != hipSuccess) return hs::hip_fail(e, "hipMalloc");
-    rc = run(p, N_G, A, B, T_AA, T_AB, T_BB, U, H, S, static_cast<char *>(ws), nullptr, nullptr,
-             nullptr);
+    rc = run(p, N_G, HS_FP64, A, B, T_AA, T_AB, T_BB, U, H, S, static_cast<char *>(ws), nullptr,
+             nullptr, nullptr);
     e = hipStreamSynchronize(nullptr);
     if (rc == HS_OK && e != hipSuccess) rc = hs::hip_fail(e, "hs_build execution");
     hipError_t e2 = hipFree(ws);

@@ -42,18 +42,42 @@ hipError_t launch_atom(const Atoms &at, int n_g, const double2 *A, const double2
                        double2 *Z, double2 *W, hipStream_t st);
 
 // Large reductions (Alg. 1 l.10, 13-15, 28-29) into the lower triangles of
-// H and S, then conjugate mirroring of the upper triangles.
-// `mid_event` (optional) is recorded between the reduction and the mirror.
+// H and S (complex FP64 MFMA).
 hipError_t launch_reduce(int K, int n_g, const double2 *A, const double2 *B,
                          const double2 *Z, const double2 *W, const int *sel,
-                         const double *d, double2 *H, double2 *S, hipStream_t st,
-                         hipEvent_t mid_event);
+                         const double *d, double2 *H, double2 *S, hipStream_t st);
 
 // Error bookkeeping shared by the C entry points (thread-local message).
 void set_error(const std::string &msg);
 const std::string &last_error();
 int hip_fail(hipError_t e, const char *where);   // records the message, returns HS_ERR_HIP
 int check_device();                              // HS_OK on gfx950, else an error status
+inline bool valid_mode(int mode) { return mode == 0 || mode == 1; }   // HS_FP64, HS_SPLIT_F16
+
+// Split-precision reductions (k_split.hip). A sliced operand: rows of X (or
+// of Xalt where sel[k] != 0), optionally scaled by sqrt(rscale[k]); outputs
+// the column maxima mx [N_G] (bit patterns of doubles) and the FP16 slices
+// S [4][groups][N_G][8], groups = 4 * ceil(K / 16).
+struct SliceSrc {
+    const double2 *X;
+    const double2 *Xalt;
+    const int *sel;
+    const double *rscale;
+    unsigned long long *mx;
+    _Float16 *S;
+};
+struct SliceView {
+    const _Float16 *S;
+    const unsigned long long *mx;
+};
+size_t split_slice_bytes(int K, int n_g);
+hipError_t launch_slice(const SliceSrc &src, int K, int n_g, hipStream_t st);
+// H segments (Z,B), (B,Z), (P3,W); S segments (A,A), (Bs,Bs): [segment][P or Q]
+hipError_t launch_split_reduce(int K, int n_g, const SliceView (&hseg)[3][2],
+                               const SliceView (&sseg)[2][2], double2 *H, double2 *S,
+                               hipStream_t st);
+// upper := conj(lower), Im(diag) := 0 for both outputs
+hipError_t launch_mirror(double2 *H, double2 *S, int n_g, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Host-side plan of one atom set and the enqueue steps shared by the one-shot
@@ -69,8 +93,9 @@ struct AtomPlan {
     int make(int N_A, const int32_t *nl_per_atom, int N_L);
     // Device bytes of the k-independent buffers (AtomBufs).
     size_t atom_bytes() const;
-    // Device bytes of the per-k-point buffers (Z, W) for N_G.
-    size_t kpoint_bytes(int n_g) const;
+    // Device bytes of the per-k-point buffers for N_G (Z, W; plus the
+    // sliced operands in the split-precision mode).
+    size_t kpoint_bytes(int n_g, int mode = 0) const;
 };
 
 // k-independent device buffers of an atom set, carved from one allocation.
@@ -86,9 +111,12 @@ struct AtomBufs {
 };
 
 // Per-k-point device buffers.
+constexpr int NSPLIT = 6;   // sliced operands: A, U B, Z, B, P3 (W or A by row), W
 struct KpointBufs {
     double2 *Z, *W;   // [K][N_G] each
-    void carve(const AtomPlan &p, int n_g, char *base);
+    _Float16 *sl[NSPLIT];
+    unsigned long long *mx[NSPLIT];
+    void carve(const AtomPlan &p, int n_g, int mode, char *base);
 };
 
 // Tables, per-atom Cholesky and operand preparation (k-independent).
@@ -96,8 +124,9 @@ hipError_t enqueue_atoms(const AtomPlan &p, const AtomBufs &ab, const double2 *T
                          const double2 *T_BB, const double2 *U, int *info_out, hipStream_t st);
 // Per-atom products and the reductions for one k-point. ev: optional phase
 // events [1..4] as in hs_options.phase_events (ev[0] is recorded by the caller).
-hipError_t enqueue_kpoint(const AtomPlan &p, const AtomBufs &ab, int n_g, const double2 *A,
-                          const double2 *B, const double2 *T_AB, const KpointBufs &kb,
-                          double2 *H, double2 *S, hipStream_t st, const hipEvent_t *ev);
+hipError_t enqueue_kpoint(const AtomPlan &p, const AtomBufs &ab, int n_g, int mode,
+                          const double2 *A, const double2 *B, const double2 *T_AB,
+                          const KpointBufs &kb, double2 *H, double2 *S, hipStream_t st,
+                          const hipEvent_t *ev);
 
 }  // namespace hs

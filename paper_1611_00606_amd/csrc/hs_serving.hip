@@ -39,10 +39,10 @@ namespace {
 constexpr size_t ALIGN = 256;
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
-size_t footprint(const hs::AtomPlan &p, int n_g) {
+size_t footprint(const hs::AtomPlan &p, int n_g, int mode) {
     const size_t ab = align_up(16 * (size_t)p.K * (size_t)n_g);
     const size_t hs = align_up(16 * (size_t)n_g * (size_t)n_g);
-    return 2 * ab + 2 * hs + p.kpoint_bytes(n_g);
+    return 2 * ab + 2 * hs + p.kpoint_bytes(n_g, mode);
 }
 
 }  // namespace
@@ -102,13 +102,13 @@ int hs_ctx_info(const hs_ctx *ctx, int32_t *info_host) {
 }
 
 size_t hs_ctx_workspace_bytes(const hs_ctx *ctx, int N_G, int mode) {
-    if (!ctx || N_G < 1 || mode != HS_FP64) return 0;
-    return ctx->plan.kpoint_bytes(N_G);
+    if (!ctx || N_G < 1 || !hs::valid_mode(mode)) return 0;
+    return ctx->plan.kpoint_bytes(N_G, mode);
 }
 
 size_t hs_ctx_footprint_bytes(const hs_ctx *ctx, int N_G, int mode) {
-    if (!ctx || N_G < 1 || mode != HS_FP64) return 0;
-    return footprint(ctx->plan, N_G);
+    if (!ctx || N_G < 1 || !hs::valid_mode(mode)) return 0;
+    return footprint(ctx->plan, N_G, mode);
 }
 
 int hs_ctx_build(const hs_ctx *ctx, const hs_complex *A, const hs_complex *B, int N_G,
@@ -119,8 +119,8 @@ int hs_ctx_build(const hs_ctx *ctx, const hs_complex *A, const hs_complex *B, in
     if (N_G < 1) return -4;
     if (!H) return -5;
     if (!S) return -6;
-    if (!opt || opt->mode != HS_FP64) return -7;
-    if (!opt->workspace || opt->workspace_bytes < ctx->plan.kpoint_bytes(N_G))
+    if (!opt || !hs::valid_mode(opt->mode)) return -7;
+    if (!opt->workspace || opt->workspace_bytes < ctx->plan.kpoint_bytes(N_G, opt->mode))
         return HS_ERR_WORKSPACE;
     hipStream_t st = static_cast<hipStream_t>(opt->stream);
     hipEvent_t ev[HS_NUM_PHASE_EVENTS] = {};
@@ -130,8 +130,8 @@ int hs_ctx_build(const hs_ctx *ctx, const hs_complex *A, const hs_complex *B, in
     hipError_t e;
     if (ev[0] && (e = hipEventRecord(ev[0], st)) != hipSuccess) return hs::hip_fail(e, "phase event");
     hs::KpointBufs kb;
-    kb.carve(ctx->plan, N_G, static_cast<char *>(opt->workspace));
-    e = hs::enqueue_kpoint(ctx->plan, ctx->ab, N_G, reinterpret_cast<const double2 *>(A),
+    kb.carve(ctx->plan, N_G, opt->mode, static_cast<char *>(opt->workspace));
+    e = hs::enqueue_kpoint(ctx->plan, ctx->ab, N_G, opt->mode, reinterpret_cast<const double2 *>(A),
                            reinterpret_cast<const double2 *>(B), ctx->T_AB, kb,
                            reinterpret_cast<double2 *>(H), reinterpret_cast<double2 *>(S), st, ev);
     return e == hipSuccess ? HS_OK : hs::hip_fail(e, "hs_ctx_build launch");
@@ -245,7 +245,7 @@ int launch(hs_server *s, Live *l) {
     hs_complex *B = reinterpret_cast<hs_complex *>(base + ab);
     hs_complex *H = reinterpret_cast<hs_complex *>(base + 2 * ab);
     hs_complex *S = reinterpret_cast<hs_complex *>(base + 2 * ab + hsz);
-    char *ws = base + 2 * ab + 2 * hsz;
+    char *ws = base + 2 * ab + 2 * hsz;   // workspace sized for the server's mode
     hipStream_t st = s->streams[l->slot];
     const size_t row = 16 * (size_t)n_g, pitch = 16 * (size_t)l->req.ld;
     hipError_t e = hipMemcpy2DAsync(A, row, l->req.A_host, pitch, row, p.K, hipMemcpyHostToDevice, st);
@@ -256,7 +256,7 @@ int launch(hs_server *s, Live *l) {
     std::memset(&opt, 0, sizeof(opt));
     opt.stream = st;
     opt.workspace = ws;
-    opt.workspace_bytes = p.kpoint_bytes(n_g);
+    opt.workspace_bytes = p.kpoint_bytes(n_g, s->mode);
     opt.mode = s->mode;
     int rc = hs_ctx_build(s->ctx, A, B, n_g, H, S, &opt);
     if (rc != HS_OK) return rc;
@@ -273,7 +273,7 @@ int hs_server_create(hs_ctx *ctx, int n_slots, size_t arena_bytes, int mode, hs_
     if (!ctx) return -1;
     if (n_slots < 1 || n_slots > 64) return -2;
     if (arena_bytes == 0) return -3;
-    if (mode != HS_FP64) return -4;
+    if (!hs::valid_mode(mode)) return -4;
     if (!out) return -5;
     *out = nullptr;
     std::unique_ptr<hs_server> s(new hs_server);
@@ -305,13 +305,13 @@ int hs_server_create(hs_ctx *ctx, int n_slots, size_t arena_bytes, int mode, hs_
 int hs_server_submit(hs_server *s, const hs_request *req) {
     if (!s) return -1;
     if (!req || req->N_G < 1 || !req->A_host || !req->B_host || req->ld < req->N_G) return -2;
-    if (footprint(s->ctx->plan, req->N_G) > s->arena_bytes) {
+    if (footprint(s->ctx->plan, req->N_G, s->mode) > s->arena_bytes) {
         hs::set_error("request footprint exceeds the server arena");
         return HS_ERR_NOMEM;
     }
     Live *l = new Live;
     l->req = *req;
-    l->bytes = footprint(s->ctx->plan, req->N_G);
+    l->bytes = footprint(s->ctx->plan, req->N_G, s->mode);
     l->epoch = s->epoch;
     l->t_submit = s->now();
     s->queue.push_back(l);

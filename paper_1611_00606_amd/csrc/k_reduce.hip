@@ -16,7 +16,8 @@
 // banded tile order, and the blocks resident on one XCD share the column
 // panels they read through that XCD's L2.
 //
-// k_mirror then completes both outputs: upper = conj(lower), Im(diag) = 0.
+// k_mirror (launched separately, also after the split-precision reduction)
+// completes both outputs: upper = conj(lower), Im(diag) = 0.
 #include "hs_internal.h"
 #include "zmfma_tile.h"
 
@@ -193,8 +194,7 @@ k_mirror(double2 *H, double2 *S, int n_g) {
 
 hipError_t launch_reduce(int K, int n_g, const double2 *A, const double2 *B,
                          const double2 *Z, const double2 *W, const int *sel,
-                         const double *d, double2 *H, double2 *S, hipStream_t st,
-                         hipEvent_t mid_event) {
+                         const double *d, double2 *H, double2 *S, hipStream_t st) {
     using C = RedCfg;
     RedArgs args;
     args.A = A;
@@ -211,12 +211,10 @@ hipError_t launch_reduce(int K, int n_g, const double2 *A, const double2 *B,
     args.ntri = args.nt * (args.nt + 1) / 2;
     args.ntri8 = (args.ntri + 7) / 8 * 8;
     hipLaunchKernelGGL(k_reduce, dim3(2 * args.ntri8), dim3(C::NT), 0, st, args);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (mid_event) {
-        e = hipEventRecord(mid_event, st);
-        if (e != hipSuccess) return e;
-    }
+    return hipGetLastError();
+}
+
+hipError_t launch_mirror(double2 *H, double2 *S, int n_g, hipStream_t st) {
     const int mt = (n_g + MT - 1) / MT;
     hipLaunchKernelGGL(k_mirror, dim3(mt, mt, 2), dim3(256), 0, st, H, S, n_g);
     return hipGetLastError();

@@ -43,15 +43,16 @@ class Context:
     def info(self) -> np.ndarray:
         return B.hs_ctx_info(self.handle, self.N_A)
 
-    def footprint_bytes(self, n_g: int) -> int:
-        return B.hs_ctx_footprint_bytes(self.handle, n_g)
+    def footprint_bytes(self, n_g: int, mode: int = B.HS_FP64) -> int:
+        return B.hs_ctx_footprint_bytes(self.handle, n_g, mode)
 
-    def workspace_bytes(self, n_g: int) -> int:
-        return B.hs_ctx_workspace_bytes(self.handle, n_g)
+    def workspace_bytes(self, n_g: int, mode: int = B.HS_FP64) -> int:
+        return B.hs_ctx_workspace_bytes(self.handle, n_g, mode)
 
-    def build(self, A, Bm, n_g, H, S, workspace, stream=None, phase_events=None):
+    def build(self, A, Bm, n_g, H, S, workspace, stream=None, phase_events=None,
+              mode: int = B.HS_FP64):
         return B.hs_ctx_build(self.handle, A, Bm, n_g, H, S, workspace=workspace, stream=stream,
-                              phase_events=phase_events)
+                              phase_events=phase_events, mode=mode)
 
     def close(self):
         if self.handle:
@@ -94,9 +95,10 @@ def percentile(x: Sequence[float], q: float) -> float:
 class ServingLoop:
     """One hs_server over a Context: n_slots streams and a device arena."""
 
-    def __init__(self, ctx: Context, n_slots: int, arena_bytes: int):
+    def __init__(self, ctx: Context, n_slots: int, arena_bytes: int, mode: int = B.HS_FP64):
         self.ctx = ctx
-        self.handle = B.hs_server_create(ctx.handle, n_slots, arena_bytes)
+        self.mode = int(mode)
+        self.handle = B.hs_server_create(ctx.handle, n_slots, arena_bytes, mode)
         self.arena_bytes = int(arena_bytes)
         self.n_slots = int(n_slots)
 

@@ -139,3 +139,12 @@ def test_context_and_server_argument_checks():
     assert lib.hs_server_pending(None) == 0
     assert lib.hs_server_used_bytes(None) == 0
     assert lib.hs_server_now(None) == 0.0
+
+
+def test_split_mode_workspace():
+    fp64 = P.hs_workspace_bytes(10, None, 49, 1000, P.HS_FP64)
+    split = P.hs_workspace_bytes(10, None, 49, 1000, P.HS_SPLIT_F16)
+    K = 490
+    groups = (K + 15) // 16 * 4
+    assert split >= fp64 + 6 * 4 * groups * 1000 * 16
+    assert P.hs_workspace_bytes(10, None, 49, 1000, 2) == 0

@@ -1,0 +1,146 @@
+"""Split-precision form (HS_SPLIT_F16) against the CPU oracle.
+
+The tolerance is the spec one for this form: relative Frobenius error
+<= 1e-9 for H and for S, each stated separately. The outputs stay exactly
+Hermitian (the lower triangle is computed and mirrored) and the Cholesky flags
+are the FP64 ones.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from hs_inputs import cn, make_config, make_problem
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+SPLIT = 1
+
+
+def _run(p, mode=SPLIT):
+    import torch
+    from paper_1611_00606_amd import DeviceBuild
+    print(f"case N_A={p.N_A} nl={sorted(set(p.nl.tolist()))} N_G={p.N_G} mode={mode}", flush=True)
+    r = DeviceBuild.from_problem(p, mode=mode)
+    r.run()
+    torch.cuda.synchronize()
+    return r
+
+
+def _rel(x, y):
+    return np.linalg.norm(x - y) / np.linalg.norm(y)
+
+
+def _expected_info(p):
+    info = np.zeros(p.N_A, np.int32)
+    for a in p.failing:
+        info[a] = 1
+    for a, piv in p.planted.items():
+        info[a] = piv
+    return info
+
+
+def _check(p, r):
+    H, S, info = r.results()
+    Hr = O.hamiltonian(p.A, p.B, p.T_AA, p.T_AB, p.T_BB, p.nl)
+    Sr = O.overlap(p.A, p.B, p.U, p.nl)
+    eh, es = _rel(H, Hr), _rel(S, Sr)
+    print(f"  split rel err H {eh:.2e} S {es:.2e}", flush=True)
+    assert eh <= TOL and es <= TOL, (eh, es)
+    assert np.array_equal(H, H.conj().T) and np.array_equal(S, S.conj().T)
+    assert np.array_equal(info, _expected_info(p))
+    return eh, es
+
+
+def _zero_columns(p, cols):
+    q = p.copy()
+    q.A[:, cols] = 0
+    q.B[:, cols] = 0
+    return q
+
+
+def _wide_range(p, seed=0):
+    """Rows of A and B scaled by factors spanning 2^-20..2^20 (a stress of the
+    per-column scaling; not a distribution the paper gives)."""
+    q = p.copy()
+    rng = np.random.default_rng(seed)
+    f = 2.0 ** rng.uniform(-20, 20, size=q.K)
+    q.A *= f[:, None]
+    q.B *= f[::-1][:, None]
+    return q
+
+
+CASES = {
+    "plain_tiny": lambda: make_config("plain_tiny", seed=0),
+    "plain_gpu_failing": lambda: make_config("plain_gpu", seed=0),
+    "ragged": lambda: make_problem(3, 7, 129, seed=3, fail_atoms=[1]),
+    "mixed_nl": lambda: make_problem(5, [16, 49, 81, 121, 3], 500, seed=4, planted={2: 40}),
+    "one_element": lambda: make_problem(1, 1, 1, seed=5),
+    "zero_columns": lambda: _zero_columns(make_problem(4, 20, 300, seed=6), [0, 17, 299]),
+    "wide_range": lambda: _wide_range(make_problem(6, 30, 400, seed=7, fail_atoms=[3])),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_split_parity(name):
+    p = CASES[name]()
+    _check(p, _run(p))
+
+
+def test_split_deterministic():
+    import torch
+    p = make_problem(4, 33, 700, seed=8, fail_atoms=[2])
+    r = _run(p)
+    H1, S1, _ = r.results()
+    r.H.zero_()
+    r.S.zero_()
+    r.run()
+    torch.cuda.synchronize()
+    H2, S2, _ = r.results()
+    assert np.array_equal(H1, H2) and np.array_equal(S1, S2)
+
+
+def test_split_full_size_sampled():
+    """N_G = 8000, N_A = 100, N_L = 81 on sampled columns and bilinear probes."""
+    import torch
+    p = make_config("precision", seed=0)
+    r = _run(p)
+    rng = np.random.default_rng(1)
+    cols = sorted(set([0, 63, 64, 4000, p.N_G - 1] + rng.integers(0, p.N_G, 6).tolist()))
+    idx = torch.as_tensor(np.asarray(cols), device=r.H.device)
+    Hc = r.H.index_select(1, idx).cpu().numpy()
+    Sc = r.S.index_select(1, idx).cpu().numpy()
+    Hr = O.hamiltonian_columns(p.A, p.B, p.T_AA, p.T_AB, p.T_BB, p.nl, cols)
+    Sr = O.overlap_columns(p.A, p.B, p.U, p.nl, cols)
+    eh, es = _rel(Hc, Hr), _rel(Sc, Sr)
+    print(f"  sampled columns: split rel err H {eh:.2e} S {es:.2e}", flush=True)
+    assert eh <= TOL and es <= TOL
+    Hd, Sd = r.H.cpu().numpy(), r.S.cpu().numpy()
+    assert np.array_equal(Hd, Hd.conj().T) and np.array_equal(Sd, Sd.conj().T)
+    for _ in range(2):
+        x, y = cn(rng, (p.N_G,)), cn(rng, (p.N_G,))
+        h, s = O.bilinear(p.A, p.B, p.T_AA, p.T_AB, p.T_BB, p.U, p.nl, x, y)
+        nx, ny = np.linalg.norm(x), np.linalg.norm(y)
+        assert abs(y.conj() @ (Hd @ x) - h) <= TOL * np.linalg.norm(Hd) * nx * ny
+        assert abs(y.conj() @ (Sd @ x) - s) <= TOL * np.linalg.norm(Sd) * nx * ny
+
+
+def test_split_in_serving_context():
+    """The resident context builds in split mode too (same result as one-shot)."""
+    import torch
+    from paper_1611_00606_amd.serving import Context
+    p = make_problem(3, 25, 450, seed=9, fail_atoms=[0])
+    r = _run(p)
+    H1, S1, _ = r.results()
+    ctx = Context(p.T_AA, p.T_AB, p.T_BB, p.U, p.nl)
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(p.A).to(dev)
+    Bm = torch.from_numpy(p.B).to(dev)
+    H = torch.empty((p.N_G, p.N_G), dtype=torch.complex128, device=dev)
+    S = torch.empty_like(H)
+    ws = torch.empty(ctx.workspace_bytes(p.N_G, SPLIT), dtype=torch.uint8, device=dev)
+    ctx.build(A, Bm, p.N_G, H, S, ws, mode=SPLIT)
+    torch.cuda.synchronize()
+    assert np.array_equal(H.cpu().numpy(), H1) and np.array_equal(S.cpu().numpy(), S1)
+    ctx.close()
