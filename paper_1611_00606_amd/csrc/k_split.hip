@@ -25,7 +25,7 @@
 // level 2: 2^23; 3: 2^23; 4: 5*2^21; 5: 6*2^21. Every FP32 addition is then
 // exact, whatever order the MFMA unit uses. Every 64 rows, and at the end of
 // each (P, Q) segment, the levels are combined in FP64,
-//     acc += 2^(eP[m] + eQ[n]) (L2 + 2^-8 L3 + 2^-16 L4 + 2^-24 L5),
+//     acc += 2^(eP[m] + eQ[n] - 16) (L2 + 2^-8 L3 + 2^-16 L4 + 2^-24 L5),
 // and cleared. The only errors left are the dropped pairs (s + t > 5) and the
 // last remainders (about 2^-40 of the column maxima) and FP64 rounding.
 #include "hs_internal.h"
@@ -276,7 +276,8 @@ __device__ __forceinline__ void split_segment(const SplitSeg sg, int n_g, int gr
         for (int i = 0; i < STM; ++i)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const double w = sP[i][v] * sQ;
+                // level c sums carry weight 2^-8c: 2^-16 for the first level
+                const double w = sP[i][v] * sQ * 0x1p-16;
                 double tr = (double)lre[i][3][v];
                 double ti = (double)lim[i][3][v];
                 tr = fma(tr, 0x1p-8, (double)lre[i][2][v]);
