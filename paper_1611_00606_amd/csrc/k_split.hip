@@ -7,7 +7,7 @@
 // Slicing (error-free): for each operand column n let e[n] be the exponent
 // with max_k max(|Re X[k][n]|, |Im X[k][n]|) < 2^e[n]. The scaled values
 // x = X 2^-e lie in (-1, 1) and are written exactly as
-//     x = sum_{s=1..4} sig_s 2^(-8 s) + r,   |r| <= 2^-33,
+//     x = sum_{s=1..5} sig_s 2^(-8 s) + r,   |r| <= 2^-41,
 // sig_1 = rint(256 x) in [-256, 256], sig_s = rint(256 r_{s-1}) in
 // [-128, 128] (r_s the running remainder, each step exact in FP64). Every
 // sig_s is a small integer, exact in FP16.
@@ -18,16 +18,19 @@
 // Im conj(p) q = P'.Q'_im; one FP16 MFMA K-step of 32 then covers 16 complex
 // contraction rows. Q'_im is formed from Q'_re in registers.
 //
-// Exact FP32 accumulation: slice pairs (s, t) with s + t <= 5 (10 pairs) are
+// Exact FP32 accumulation: slice pairs (s, t) with s + t <= 6 (15 pairs) are
 // summed into one FP32 accumulator per level c = s + t. Products are
-// integers with |sig_s sig_t| <= 2^16 (level 2), <= 2^15 (others), so over 64
-// complex rows (128 real products per pair) the level sums stay below 2^24:
-// level 2: 2^23; 3: 2^23; 4: 5*2^21; 5: 6*2^21. Every FP32 addition is then
-// exact, whatever order the MFMA unit uses. Every 64 rows, and at the end of
-// each (P, Q) segment, the levels are combined in FP64,
-//     acc += 2^(eP[m] + eQ[n] - 16) (L2 + 2^-8 L3 + 2^-16 L4 + 2^-24 L5),
-// and cleared. The only errors left are the dropped pairs (s + t > 5) and the
-// last remainders (about 2^-40 of the column maxima) and FP64 rounding.
+// integers with |sig_s sig_t| <= 2^16 (level 2), <= 2^15 or 2^14 (others), so
+// over 64 complex rows (128 real products per pair) the level sums stay
+// below 2^24: level 2: 2^23; 3: 2^23; 4: 5*2^21; 5: 6*2^21; 6: 7*2^21. Every
+// FP32 addition is then exact, whatever order the MFMA unit uses. Every 64
+// rows, and at the end of each (P, Q) segment, the levels are combined in FP64,
+//     acc += 2^(eP[m] + eQ[n] - 16) (L2 + 2^-8 L3 + ... + 2^-32 L6),
+// and cleared. The only errors left are the dropped pairs (s + t > 6, at most
+// 2^-50 each) and the last remainders (2^-41 of the column maxima), and FP64
+// rounding. Relative to a typical product (entries ~4-5 standard deviations
+// below their column maximum) that is about 2^-36. Four slices (2^-33) would
+// leave errors of a few 1e-9.
 #include "hs_internal.h"
 #include "zmfma_tile.h"
 
@@ -38,9 +41,9 @@ namespace {
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int NSL = 4;          // slices per value
+constexpr int NSL = 5;          // slices per value
 constexpr int SBITS = 8;        // bits per slice
-constexpr int NLEV = 4;         // levels c = 2..5
+constexpr int NLEV = 5;         // levels c = 2..6
 
 // ---------------------------------------------------------------------------
 // Column maxima. A positive double's bit pattern orders like the double, so
@@ -101,7 +104,7 @@ __device__ __forceinline__ int col_exp(const unsigned long long *mx, int n) {
 
 // ---------------------------------------------------------------------------
 // Slices. One thread per (group of 4 complex rows, column): 8 interleaved
-// real values -> 4 slices of 8 halves, written to S[s][g][n][0..7].
+// real values -> NSL slices of 8 halves, written to S[s][g][n][0..7].
 
 __global__ void __launch_bounds__(256)
 k_slice(SliceSrc src, int K, int n_g, int groups) {
@@ -149,6 +152,7 @@ constexpr int FLUSH = 4;              // stages per flush = 64 complex rows
 constexpr int SBAND = 8;
 // LDS per operand per stage: NSL slices x SGRP groups x 64 columns x 16 B
 constexpr int LDS_OP = NSL * SGRP * 64;   // in units of 16 B
+constexpr int LD_ITEMS = (LDS_OP + SNT - 1) / SNT;
 
 struct SplitSeg {
     const _Float16 *P, *Q;                  // slices [4][groups][n_g][8]
@@ -203,8 +207,9 @@ __device__ __forceinline__ void split_segment(const SplitSeg sg, int n_g, int gr
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave % SWM, wn = wave / SWM;
 
-    // loader: each thread moves 2 P and 2 Q 16-byte items per stage; item
-    // id = tid + j*512 -> (slice, group, column) = (id / 256, (id / 64) % 4, id % 64)
+    // loader: NSL*SGRP*64 16-byte items per operand per stage, item
+    // id -> (slice, group, column) = (id / 256, (id / 64) % 4, id % 64); each
+    // thread moves up to LD_ITEMS of them (indices clamped, extra ones unused)
     const int col = tid & 63;
     const int pm = m0 + col, qn = n0 + col;
     const bool pok = pm < n_g, qok = qn < n_g;
@@ -212,13 +217,14 @@ __device__ __forceinline__ void split_segment(const SplitSeg sg, int n_g, int gr
     const long long plane = (long long)groups * n_g;   // 16-byte items per slice
     const uint4 *Pg = reinterpret_cast<const uint4 *>(sg.P);
     const uint4 *Qg = reinterpret_cast<const uint4 *>(sg.Q);
-    uint4 rp[2], rq[2];
+    uint4 rp[LD_ITEMS], rq[LD_ITEMS];
     const int nstage = groups / SGRP;
     auto fetch = [&](int st) {
         const int st_c = st < nstage ? st : nstage - 1;   // clamped (unused past the end)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int id = tid + j * SNT;
+        for (int j = 0; j < LD_ITEMS; ++j) {
+            const int idv = tid + j * SNT;
+            const int id = idv < LDS_OP ? idv : LDS_OP - 1;
             const int s = id >> 8, gi = (id >> 6) & 3;
             const long long g = (long long)st_c * SGRP + gi;
             rp[j] = Pg[s * plane + g * n_g + pmc];
@@ -231,8 +237,9 @@ __device__ __forceinline__ void split_segment(const SplitSeg sg, int n_g, int gr
         // per-component selects (an aggregate select becomes an address select
         // that sends the staging registers to scratch)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < LD_ITEMS; ++j) {
             const int id = tid + j * SNT;
+            if (id >= LDS_OP) continue;
             uint4 a, b;
             a.x = pok ? rp[j].x : 0u;
             a.y = pok ? rp[j].y : 0u;
@@ -278,14 +285,13 @@ __device__ __forceinline__ void split_segment(const SplitSeg sg, int n_g, int gr
             for (int v = 0; v < 4; ++v) {
                 // level c sums carry weight 2^-8c: 2^-16 for the first level
                 const double w = sP[i][v] * sQ * 0x1p-16;
-                double tr = (double)lre[i][3][v];
-                double ti = (double)lim[i][3][v];
-                tr = fma(tr, 0x1p-8, (double)lre[i][2][v]);
-                ti = fma(ti, 0x1p-8, (double)lim[i][2][v]);
-                tr = fma(tr, 0x1p-8, (double)lre[i][1][v]);
-                ti = fma(ti, 0x1p-8, (double)lim[i][1][v]);
-                tr = fma(tr, 0x1p-8, (double)lre[i][0][v]);
-                ti = fma(ti, 0x1p-8, (double)lim[i][0][v]);
+                double tr = (double)lre[i][NLEV - 1][v];
+                double ti = (double)lim[i][NLEV - 1][v];
+#pragma unroll
+                for (int c = NLEV - 2; c >= 0; --c) {
+                    tr = fma(tr, 0x1p-8, (double)lre[i][c][v]);
+                    ti = fma(ti, 0x1p-8, (double)lim[i][c][v]);
+                }
                 are[i][v] = fma(tr, w, are[i][v]);
                 aim[i][v] = fma(ti, w, aim[i][v]);
             }
@@ -326,7 +332,7 @@ __device__ __forceinline__ void split_segment(const SplitSeg sg, int n_g, int gr
         for (int s = 0; s < NSL; ++s)
 #pragma unroll
             for (int t = 0; t < NSL; ++t) {
-                if (s + t >= NLEV) continue;   // 0-based: keep (s+1) + (t+1) <= 5
+                if (s + t >= NLEV) continue;   // 0-based: keep (s+1) + (t+1) <= 6
                 const int c = s + t;            // level index: level (s+1)+(t+1) = c + 2
 #pragma unroll
                 for (int i = 0; i < STM; ++i) {
@@ -342,7 +348,7 @@ __device__ __forceinline__ void split_segment(const SplitSeg sg, int n_g, int gr
 
 __global__ void __launch_bounds__(SNT)
 k_split_reduce(SplitArgs args) {
-    __shared__ uint4 lds[2 * 2 * LDS_OP];   // 2 buffers x (P, Q), 64 KiB
+    __shared__ uint4 lds[2 * 2 * LDS_OP];   // 2 buffers x (P, Q), 80 KiB
 
     int b = blockIdx.x;
     const bool isH = b < args.ntri8;
