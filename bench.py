@@ -163,7 +163,7 @@ def split_bench(p, steps: int, warmup: int, fp64_ms: float, hip, n_cols: int = 1
     Sr = oracle.overlap_columns(p.A, p.B, p.U, p.nl, cols)
     f = algorithmic_flops(p.nl, p.N_G, info)
     return {
-        "mode": "split_f16 (4 x 8-bit slices, FP16 MFMA, exact FP32 accumulation, FP64 recombination)",
+        "mode": "split_f16 (4 x 9-bit slices, FP16 MFMA, FP32 accumulation, FP64 recombination)",
         "ms_per_step": round(total, 3),
         "value": round(f / (total * 1e-3) / 1e12, 3),
         "unit": "TFLOP/s (FP64-equivalent)",

@@ -84,13 +84,13 @@ enum {
  * the per-atom products are always binary64).
  *   HS_FP64       complex binary64 MFMA.
  *   HS_SPLIT_F16  split precision: each binary64 operand column is scaled by a
- *                 power of two and cut into 5 exact 8-bit integer slices held
- *                 in FP16; the slice products (pairs s + t <= 6) run on FP16
- *                 MFMA with FP32 accumulation kept exact (integer sums below
- *                 2^24, flushed every 64 contraction rows) and are recombined
- *                 in binary64. Error about 2^-41 of the operand column maxima
- *                 per product term (relative Frobenius error of H and S below
- *                 1e-9 for the configs here). Inputs must be finite. */
+ *                 power of two and cut into 4 exact 9-bit integer slices held
+ *                 in FP16; the slice products (pairs s + t <= 5) run on FP16
+ *                 MFMA with FP32 accumulation (the two leading levels exact,
+ *                 flushed every 32 contraction rows) and are recombined in
+ *                 binary64. Error about 2^-35 of the operand column maxima per
+ *                 product term (relative Frobenius error of H and S near 1e-10
+ *                 for Gaussian operands, below 1e-9). Inputs must be finite. */
 typedef enum {
     HS_FP64 = 0,
     HS_SPLIT_F16 = 1

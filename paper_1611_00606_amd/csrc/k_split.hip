@@ -7,10 +7,11 @@
 // Slicing (error-free): for each operand column n let e[n] be the exponent
 // with max_k max(|Re X[k][n]|, |Im X[k][n]|) < 2^e[n]. The scaled values
 // x = X 2^-e lie in (-1, 1) and are written exactly as
-//     x = sum_{s=1..5} sig_s 2^(-8 s) + r,   |r| <= 2^-41,
-// sig_1 = rint(256 x) in [-256, 256], sig_s = rint(256 r_{s-1}) in
-// [-128, 128] (r_s the running remainder, each step exact in FP64). Every
-// sig_s is a small integer, exact in FP16.
+//     x = sum_{s=1..NSL} sig_s 2^(-b s) + r,   |r| <= 2^-(b NSL + 1),
+// with b = SBITS bits per slice: sig_1 = rint(2^b x) in [-2^b, 2^b] and
+// sig_s = rint(2^b r_{s-1}) in [-2^(b-1), 2^(b-1)] (r_s the running
+// remainder; every step is exact in FP64). With b <= 10 every sig_s is an
+// integer that FP16 holds exactly.
 //
 // Complex products without extra passes: along the contraction index the real
 // and imaginary parts are interleaved, P' = (p_re, p_im), Q'_re = (q_re, q_im)
@@ -18,21 +19,40 @@
 // Im conj(p) q = P'.Q'_im; one FP16 MFMA K-step of 32 then covers 16 complex
 // contraction rows. Q'_im is formed from Q'_re in registers.
 //
-// Exact FP32 accumulation: slice pairs (s, t) with s + t <= 6 (15 pairs) are
-// summed into one FP32 accumulator per level c = s + t. Products are
-// integers with |sig_s sig_t| <= 2^16 (level 2), <= 2^15 or 2^14 (others), so
-// over 64 complex rows (128 real products per pair) the level sums stay
-// below 2^24: level 2: 2^23; 3: 2^23; 4: 5*2^21; 5: 6*2^21; 6: 7*2^21. Every
-// FP32 addition is then exact, whatever order the MFMA unit uses. Every 64
-// rows, and at the end of each (P, Q) segment, the levels are combined in FP64,
-//     acc += 2^(eP[m] + eQ[n] - 16) (L2 + 2^-8 L3 + ... + 2^-32 L6),
-// and cleared. The only errors left are the dropped pairs (s + t > 6, at most
-// 2^-50 each) and the last remainders (2^-41 of the column maxima), and FP64
-// rounding. Relative to a typical product (entries ~4-5 standard deviations
-// below their column maximum) that is about 2^-36. Four slices (2^-33) would
-// leave errors of a few 1e-9.
+// Accumulation: the slice pairs (s, t) with s + t <= NSL + 1 are summed into
+// one FP32 accumulator per level c = s + t and, every FLUSH stages (16
+// complex rows each) and at the end of each (P, Q) segment, combined in FP64:
+//     acc += 2^(eP[m] + eQ[n] - 2b) (L_2 + 2^-b L_3 + 2^-2b L_4 + ...)
+// and cleared. Default scheme (b = 9, NSL = 4, FLUSH = 2, i.e. 32 rows =
+// 64 real products per pair between flushes):
+//   level 2: |sig_1 sig_1| <= 2^18, sum <= 64 * 2^18 = 2^24: exact;
+//   level 3: two pairs <= 2^17 each, sum <= 2^24: exact;
+//   levels 4, 5 (weights 2^-18, 2^-27 relative to level 2) may round, at
+//   2^-24 of their own size, i.e. below 2^-42 of the leading terms.
+// Products of FP16 integers are exact in FP32 and, within one MFMA, partial
+// sums of a level stay below 2^24, so the MFMA's internal order is immaterial.
+// Errors left: the remainders (2^-37 of the column maxima), the dropped pairs
+// (s + t > 5, at most 2^-38), and FP64 rounding; relative to a typical
+// product (entries a few standard deviations below their column maximum)
+// about 2^-32.
 #include "hs_internal.h"
 #include "zmfma_tile.h"
+
+#ifndef HS_SPLIT_NSL
+#define HS_SPLIT_NSL 4
+#endif
+#ifndef HS_SPLIT_BITS
+#define HS_SPLIT_BITS 9
+#endif
+#ifndef HS_SPLIT_FLUSH
+#define HS_SPLIT_FLUSH 2
+#endif
+#ifndef HS_SPLIT_WM
+#define HS_SPLIT_WM 4
+#endif
+#ifndef HS_SPLIT_WN
+#define HS_SPLIT_WN 2
+#endif
 
 namespace hs {
 
@@ -41,9 +61,10 @@ namespace {
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int NSL = 5;          // slices per value
-constexpr int SBITS = 8;        // bits per slice
-constexpr int NLEV = 5;         // levels c = 2..6
+constexpr int NSL = HS_SPLIT_NSL;      // slices per value
+constexpr int SBITS = HS_SPLIT_BITS;   // bits per slice
+constexpr int NLEV = NSL;              // levels c = 2 .. NSL + 1
+static_assert(SBITS <= 10, "slices must be integers FP16 holds exactly");
 
 // ---------------------------------------------------------------------------
 // Column maxima. A positive double's bit pattern orders like the double, so
@@ -141,21 +162,24 @@ k_slice(SliceSrc src, int K, int n_g, int groups) {
 // ---------------------------------------------------------------------------
 // Slice GEMM over lower-triangle tiles of H and S.
 
-constexpr int SBM = 64;           // tile rows (g')
-constexpr int SBN = 64;           // tile cols (g)
-constexpr int SWM = 2, SWN = 4;   // waves: 2 x 4, wave tile 32 x 16
+constexpr int SBM = 64;                 // tile rows (g')
+constexpr int SBN = 64;                 // tile cols (g)
+constexpr int SWM = HS_SPLIT_WM, SWN = HS_SPLIT_WN;
 constexpr int SNT = 64 * SWM * SWN;
-constexpr int STM = SBM / SWM / 16;   // 2 blocks of 16 rows per wave
-constexpr int STN = SBN / SWN / 16;   // 1 block of 16 cols per wave
-constexpr int SGRP = 4;               // groups (of 4 complex rows) per stage = 16 rows
-constexpr int FLUSH = 4;              // stages per flush = 64 complex rows
+constexpr int SWTM = SBM / SWM, SWTN = SBN / SWN;   // wave tile
+constexpr int STM = SWTM / 16;          // 16-row blocks per wave
+constexpr int STN = SWTN / 16;          // 16-col blocks per wave
+constexpr int SGRP = 4;                 // groups (of 4 complex rows) per stage = 16 rows
+constexpr int FLUSH = HS_SPLIT_FLUSH;   // stages per flush
 constexpr int SBAND = 8;
 // LDS per operand per stage: NSL slices x SGRP groups x 64 columns x 16 B
 constexpr int LDS_OP = NSL * SGRP * 64;   // in units of 16 B
 constexpr int LD_ITEMS = (LDS_OP + SNT - 1) / SNT;
+static_assert(SBM == 64 && SBN == 64, "loader assumes 64-column tiles");
+static_assert(SWTM % 16 == 0 && SWTN % 16 == 0, "wave tiling");
 
 struct SplitSeg {
-    const _Float16 *P, *Q;                  // slices [4][groups][n_g][8]
+    const _Float16 *P, *Q;                  // slices [NSL][groups][n_g][8]
     const unsigned long long *mP, *mQ;      // column maxima (bit patterns) [n_g]
 };
 
@@ -196,12 +220,16 @@ __device__ __forceinline__ void sband_tile(int t, int nt, int &ti, int &tj) {
     }
 }
 
+struct Acc64 {
+    double re[STM][STN][4];
+    double im[STM][STN][4];
+};
+
 // One (P, Q) segment into the FP64 accumulators. The segment is taken by
 // value: a reference into the by-value kernel argument would move the whole
 // argument block into scratch memory.
 __device__ __forceinline__ void split_segment(const SplitSeg sg, int n_g, int groups, int m0,
-                                              int n0, double (&are)[STM][4], double (&aim)[STM][4],
-                                              uint4 *lds) {
+                                              int n0, Acc64 &acc, uint4 *lds) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -231,11 +259,11 @@ __device__ __forceinline__ void split_segment(const SplitSeg sg, int n_g, int gr
             rq[j] = Qg[s * plane + g * n_g + qnc];
         }
     };
+    // per-component selects (an aggregate select becomes an address select
+    // that sends the staging registers to scratch)
     auto stash = [&](int buf) {
         uint4 *lp = lds + buf * 2 * LDS_OP;
         uint4 *lq = lp + LDS_OP;
-        // per-component selects (an aggregate select becomes an address select
-        // that sends the staging registers to scratch)
 #pragma unroll
         for (int j = 0; j < LD_ITEMS; ++j) {
             const int id = tid + j * SNT;
@@ -254,47 +282,53 @@ __device__ __forceinline__ void split_segment(const SplitSeg sg, int n_g, int gr
         }
     };
 
-    // column scales of this lane's accumulator rows (g') and column (g)
-    double sP[STM][4], sQ;
+    // column scales of this lane's accumulator rows (g') and columns (g),
+    // with the 2^-2b weight of the first level folded in
+    double sP[STM][4], sQ[STN];
 #pragma unroll
     for (int i = 0; i < STM; ++i)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + v;
-            sP[i][v] = ldexp(1.0, col_exp(sg.mP, m < n_g ? m : n_g - 1));
+            const int m = m0 + wm * SWTM + i * 16 + 4 * (lane >> 4) + v;
+            sP[i][v] = ldexp(1.0, col_exp(sg.mP, m < n_g ? m : n_g - 1) - 2 * SBITS);
         }
-    {
-        const int n = n0 + wn * 16 + (lane & 15);
-        sQ = ldexp(1.0, col_exp(sg.mQ, n < n_g ? n : n_g - 1));
+#pragma unroll
+    for (int j = 0; j < STN; ++j) {
+        const int n = n0 + wn * SWTN + j * 16 + (lane & 15);
+        sQ[j] = ldexp(1.0, col_exp(sg.mQ, n < n_g ? n : n_g - 1));
     }
 
-    f4 lre[STM][NLEV], lim[STM][NLEV];
+    f4 lre[STM][STN][NLEV], lim[STM][STN][NLEV];
     auto clear = [&]() {
 #pragma unroll
         for (int i = 0; i < STM; ++i)
 #pragma unroll
-            for (int c = 0; c < NLEV; ++c) {
-                lre[i][c] = f4{0.f, 0.f, 0.f, 0.f};
-                lim[i][c] = f4{0.f, 0.f, 0.f, 0.f};
-            }
+            for (int j = 0; j < STN; ++j)
+#pragma unroll
+                for (int c = 0; c < NLEV; ++c) {
+                    lre[i][j][c] = f4{0.f, 0.f, 0.f, 0.f};
+                    lim[i][j][c] = f4{0.f, 0.f, 0.f, 0.f};
+                }
     };
+    constexpr double STEP = 1.0 / (double)(1 << SBITS);
     auto flush = [&]() {
 #pragma unroll
         for (int i = 0; i < STM; ++i)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                // level c sums carry weight 2^-8c: 2^-16 for the first level
-                const double w = sP[i][v] * sQ * 0x1p-16;
-                double tr = (double)lre[i][NLEV - 1][v];
-                double ti = (double)lim[i][NLEV - 1][v];
+            for (int j = 0; j < STN; ++j)
 #pragma unroll
-                for (int c = NLEV - 2; c >= 0; --c) {
-                    tr = fma(tr, 0x1p-8, (double)lre[i][c][v]);
-                    ti = fma(ti, 0x1p-8, (double)lim[i][c][v]);
+                for (int v = 0; v < 4; ++v) {
+                    const double w = sP[i][v] * sQ[j];
+                    double tr = (double)lre[i][j][NLEV - 1][v];
+                    double ti = (double)lim[i][j][NLEV - 1][v];
+#pragma unroll
+                    for (int c = NLEV - 2; c >= 0; --c) {
+                        tr = fma(tr, STEP, (double)lre[i][j][c][v]);
+                        ti = fma(ti, STEP, (double)lim[i][j][c][v]);
+                    }
+                    acc.re[i][j][v] = fma(tr, w, acc.re[i][j][v]);
+                    acc.im[i][j][v] = fma(ti, w, acc.im[i][j][v]);
                 }
-                are[i][v] = fma(tr, w, are[i][v]);
-                aim[i][v] = fma(ti, w, aim[i][v]);
-            }
         clear();
     };
 
@@ -309,35 +343,39 @@ __device__ __forceinline__ void split_segment(const SplitSeg sg, int n_g, int gr
         fetch(st + 1);
         const uint4 *lp = lds + (st & 1) * 2 * LDS_OP;
         const uint4 *lq = lp + LDS_OP;
-        h8 a[STM][NSL], bre[NSL], bim[NSL];
+        h8 a[STM][NSL], bre[STN][NSL];
 #pragma unroll
         for (int s = 0; s < NSL; ++s) {
 #pragma unroll
             for (int i = 0; i < STM; ++i) {
-                const uint4 u = lp[(s * SGRP + lg) * 64 + wm * 32 + i * 16 + lc];
+                const uint4 u = lp[(s * SGRP + lg) * 64 + wm * SWTM + i * 16 + lc];
                 a[i][s] = __builtin_bit_cast(h8, u);
             }
-            const uint4 u = lq[(s * SGRP + lg) * 64 + wn * 16 + lc];
-            const h8 b = __builtin_bit_cast(h8, u);
-            bre[s] = b;
-            h8 bi;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                bi[2 * q] = b[2 * q + 1];
-                bi[2 * q + 1] = -b[2 * q];
+            for (int j = 0; j < STN; ++j) {
+                const uint4 u = lq[(s * SGRP + lg) * 64 + wn * SWTN + j * 16 + lc];
+                bre[j][s] = __builtin_bit_cast(h8, u);
             }
-            bim[s] = bi;
         }
 #pragma unroll
-        for (int s = 0; s < NSL; ++s)
+        for (int t = 0; t < NSL; ++t)
 #pragma unroll
-            for (int t = 0; t < NSL; ++t) {
-                if (s + t >= NLEV) continue;   // 0-based: keep (s+1) + (t+1) <= 6
-                const int c = s + t;            // level index: level (s+1)+(t+1) = c + 2
+            for (int j = 0; j < STN; ++j) {
+                const h8 b = bre[j][t];
+                h8 bi;
 #pragma unroll
-                for (int i = 0; i < STM; ++i) {
-                    lre[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[i][s], bre[t], lre[i][c], 0, 0, 0);
-                    lim[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[i][s], bim[t], lim[i][c], 0, 0, 0);
+                for (int q = 0; q < 4; ++q) {
+                    bi[2 * q] = b[2 * q + 1];
+                    bi[2 * q + 1] = -b[2 * q];
+                }
+#pragma unroll
+                for (int s = 0; s + t < NLEV; ++s) {   // levels (s+1)+(t+1) <= NSL+1
+                    const int c = s + t;
+#pragma unroll
+                    for (int i = 0; i < STM; ++i) {
+                        lre[i][j][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[i][s], b, lre[i][j][c], 0, 0, 0);
+                        lim[i][j][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[i][s], bi, lim[i][j][c], 0, 0, 0);
+                    }
                 }
             }
         stash((st + 1) & 1);
@@ -348,7 +386,7 @@ __device__ __forceinline__ void split_segment(const SplitSeg sg, int n_g, int gr
 
 __global__ void __launch_bounds__(SNT)
 k_split_reduce(SplitArgs args) {
-    __shared__ uint4 lds[2 * 2 * LDS_OP];   // 2 buffers x (P, Q), 80 KiB
+    __shared__ uint4 lds[2 * 2 * LDS_OP];   // 2 buffers x (P, Q)
 
     int b = blockIdx.x;
     const bool isH = b < args.ntri8;
@@ -362,34 +400,40 @@ k_split_reduce(SplitArgs args) {
     const int m0 = ti * SBM, n0 = tj * SBN;
     const int n_g = args.n_g;
 
-    double are[STM][4], aim[STM][4];
+    Acc64 acc;
 #pragma unroll
     for (int i = 0; i < STM; ++i)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) are[i][v] = aim[i][v] = 0.0;
+        for (int j = 0; j < STN; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc.re[i][j][v] = acc.im[i][j][v] = 0.0;
 
     if (isH) {
         const SplitSeg h0 = args.h[0], h1 = args.h[1], h2 = args.h[2];
-        split_segment(h0, n_g, args.groups, m0, n0, are, aim, lds);
-        split_segment(h1, n_g, args.groups, m0, n0, are, aim, lds);
-        split_segment(h2, n_g, args.groups, m0, n0, are, aim, lds);
+        split_segment(h0, n_g, args.groups, m0, n0, acc, lds);
+        split_segment(h1, n_g, args.groups, m0, n0, acc, lds);
+        split_segment(h2, n_g, args.groups, m0, n0, acc, lds);
     } else {
         const SplitSeg s0 = args.s[0], s1 = args.s[1];
-        split_segment(s0, n_g, args.groups, m0, n0, are, aim, lds);
-        split_segment(s1, n_g, args.groups, m0, n0, are, aim, lds);
+        split_segment(s0, n_g, args.groups, m0, n0, acc, lds);
+        split_segment(s1, n_g, args.groups, m0, n0, acc, lds);
     }
 
     double2 *out = isH ? args.H : args.S;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave % SWM, wn = wave / SWM;
-    const int g = n0 + wn * 16 + (lane & 15);
 #pragma unroll
-    for (int i = 0; i < STM; ++i)
+    for (int j = 0; j < STN; ++j) {
+        const int g = n0 + wn * SWTN + j * 16 + (lane & 15);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int gp = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + v;
-            if (gp < n_g && g <= gp) out[(long long)gp * n_g + g] = double2{are[i][v], aim[i][v]};
-        }
+        for (int i = 0; i < STM; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gp = m0 + wm * SWTM + i * 16 + 4 * (lane >> 4) + v;
+                if (gp < n_g && g <= gp)
+                    out[(long long)gp * n_g + g] = double2{acc.re[i][j][v], acc.im[i][j][v]};
+            }
+    }
 }
 
 }  // namespace
