@@ -96,6 +96,17 @@ typedef enum {
     HS_SPLIT_F16 = 1
 } hs_mode;
 
+/* Tile shapes of the batched per-atom stage (see hs_options.batch): shape id
+ * -> (BM rows of an atom's N_L, BN columns of N_G) per tile, listed by
+ * hs_tile_config. */
+#define HS_NUM_TILE_CONFIGS 6
+
+/* Tile shape id for each N_L (entry [N_L], 1 <= N_L <= HS_MAX_NL; entry 0
+ * unused), as filled by hs_autotune_atoms. */
+typedef struct {
+    unsigned char cfg[HS_MAX_NL + 1];
+} hs_tuning;
+
 typedef struct {
     /* hipStream_t to enqueue on; NULL = the default (null) stream. */
     void *stream;
@@ -119,8 +130,20 @@ typedef struct {
        [0] start, [1] after the per-atom Cholesky and operand preparation,
        [2] after the per-atom products (Alg. 1 first loop and second-loop
        branches), [3] after the large lower-triangle reductions of H and S,
-       [4] after the conjugate mirroring (end of the build). */
+       [4] after the conjugate mirroring (end of the build). With batch = 1
+       the preparation runs inside the batched launch: [1] is recorded right
+       after [0] and [1]..[2] covers preparation and products. */
     void **phase_events;
+    /* 0: per-atom preparation and products as separate launches, one tile
+       shape for all atoms (the largest N_L decides). 1: batched form - one
+       persistent launch runs every atom's Cholesky (with its failure test)
+       and every atom's Z_a and W_a tiles, each atom with the tile shape of
+       its N_L. Same results up to rounding order. */
+    int batch;
+    /* HOST hs_tuning or NULL (built-in shapes: N_L <= 32 -> 32x256,
+       <= 64 -> 64x128, else 128x64). Used when batch = 1; every N_L in use
+       must map to an id < HS_NUM_TILE_CONFIGS. */
+    const hs_tuning *tuning;
 } hs_options;
 
 #define HS_NUM_PHASE_EVENTS 5
@@ -166,6 +189,32 @@ int hs_build_ex(const hs_complex *A, const hs_complex *B,
 /* Human-readable text for a status code (thread-local last HIP message for 1). */
 const char *hs_status_string(int status);
 
+/*
+ * hs_tile_config - shape of batched tile id `id`: *bm rows of an atom's
+ * N_L by *bn columns of N_G (either pointer may be NULL). Returns 0, or -1
+ * for an id outside [0, HS_NUM_TILE_CONFIGS).
+ */
+int hs_tile_config(int id, int *bm, int *bn);
+
+/*
+ * hs_autotune_atoms - measures every tile shape of the batched per-atom stage
+ * on the current device and picks the fastest per N_L.
+ * For each of the n_values N_L values (host int32 array, each in
+ * [1, HS_MAX_NL]) it builds a synthetic atom set of that N_L (about 2048
+ * rows, HPD T^AA blocks) at N_G columns, prepares it once, then times the
+ * batched product launch with each shape `reps` times (HIP events on
+ * `stream`, NULL = default stream) and keeps the minimum.
+ * out (host): entries of the listed N_L values get the fastest id, all
+ * other entries the built-in choice. ms (host, optional): [n_values]
+ * [HS_NUM_TILE_CONFIGS] minimum times in milliseconds.
+ * Allocates and frees its own device memory and synchronizes `stream`: call
+ * it at set-up, not inside a build loop.
+ * Returns 0, -1 (nl_values NULL), -2 (n_values < 1 or an entry out of
+ * range), -3 (N_G < 1), -4 (reps < 1), -6 (out NULL), or a status >= 1.
+ */
+int hs_autotune_atoms(const int32_t *nl_values, int n_values, int N_G, int reps,
+                      void *stream, hs_tuning *out, float *ms);
+
 /* ------------------------------------------------------------------------
  * Resident context: one atom set, many k-points.
  *
@@ -207,8 +256,10 @@ size_t hs_ctx_footprint_bytes(const hs_ctx *ctx, int N_G, int mode);
  * hs_ctx_build - enqueue one k-point on opt->stream (asynchronous, like
  * hs_build_ex). Arguments: 1 ctx, 2 A, 3 B ([K][N_G] device), 4 N_G >= 1,
  * 5 H, 6 S ([N_G][N_G] device), 7 opt (stream, workspace, mode,
- * phase_events are used; info and nl_per_atom are ignored: the context
- * holds them). Concurrent calls on different streams with different
+ * phase_events, batch and tuning are used; info and nl_per_atom are ignored:
+ * the context holds them; with batch = 1 the cached preparation is reused
+ * and the batched launch runs the products only). Concurrent calls on
+ * different streams with different
  * workspaces and outputs are allowed; results are bitwise identical to a
  * build of the same inputs alone.
  */

@@ -16,7 +16,9 @@ from ._binding import (  # noqa: F401
     HS_SPLIT_F16,
     HS_MAX_NL,
     HS_NUM_PHASE_EVENTS,
+    HS_NUM_TILE_CONFIGS,
     HSError,
+    hs_tuning,
     LIB_PATH,
     load_library,
     hs_build,
@@ -41,5 +43,7 @@ from ._binding import (  # noqa: F401,E402
     hs_server_used_bytes,
     hs_server_now,
     hs_server_destroy,
+    hs_tile_config,
+    hs_autotune_atoms,
 )
 from .runner import DeviceBuild  # noqa: F401,E402

@@ -27,12 +27,17 @@ HS_FP64 = 0
 HS_SPLIT_F16 = 1
 HS_MAX_NL = 128
 HS_NUM_PHASE_EVENTS = 5
+HS_NUM_TILE_CONFIGS = 6
 
 
 class HSError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"hs_build status {status}: {message}")
         self.status = status
+
+
+class hs_tuning(ctypes.Structure):
+    _fields_ = [("cfg", ctypes.c_ubyte * (HS_MAX_NL + 1))]
 
 
 class hs_options(ctypes.Structure):
@@ -44,6 +49,8 @@ class hs_options(ctypes.Structure):
         ("mode", ctypes.c_int),
         ("nl_per_atom", ctypes.POINTER(ctypes.c_int32)),
         ("phase_events", ctypes.POINTER(ctypes.c_void_p)),
+        ("batch", ctypes.c_int),
+        ("tuning", ctypes.POINTER(hs_tuning)),
     ]
 
 
@@ -130,6 +137,12 @@ def load_library() -> ctypes.CDLL:
     lib.hs_server_now.restype = ctypes.c_double
     lib.hs_server_destroy.argtypes = [vp]
     lib.hs_server_destroy.restype = None
+    ip = ctypes.POINTER(ctypes.c_int)
+    lib.hs_tile_config.argtypes = [i32, ip, ip]
+    lib.hs_tile_config.restype = i32
+    lib.hs_autotune_atoms.argtypes = [i32p, i32, i32, i32, vp, ctypes.POINTER(hs_tuning),
+                                      ctypes.POINTER(ctypes.c_float)]
+    lib.hs_autotune_atoms.restype = i32
     _lib = lib
     return lib
 
@@ -184,15 +197,25 @@ def hs_build(A, B, T_AA, T_AB, T_BB, U, N_A, N_L, N_G, H, S, check: bool = True)
     return _raise(rc, check)
 
 
+def _tuning_ptr(tuning):
+    if tuning is None:
+        return None
+    if not isinstance(tuning, hs_tuning):
+        raise TypeError("tuning must be an hs_tuning")
+    return ctypes.pointer(tuning)
+
+
 def hs_build_ex(A, B, T_AA, T_AB, T_BB, U, N_A, N_L, N_G, H, S, *, workspace,
                 info=None, stream=None, mode: int = HS_FP64, nl_per_atom=None,
-                phase_events=None, check: bool = True) -> int:
+                phase_events=None, batch: int = 0, tuning=None, check: bool = True) -> int:
     """Asynchronous build on `stream` (default: torch's current stream).
 
     workspace: uint8 device tensor of >= hs_workspace_bytes(...) bytes.
     info: int32 device tensor [N_A] or None.
     nl_per_atom: host sequence of N_A ints, or None for a uniform N_L.
     phase_events: None or a sequence of HS_NUM_PHASE_EVENTS raw hipEvent_t handles.
+    batch: 1 runs the per-atom stage as the batched persistent launch.
+    tuning: None or an hs_tuning (tile shape per N_L) for the batched launch.
     """
     import torch
     _check_c128(A, B, T_AA, T_AB, T_BB, U, H, S)
@@ -210,6 +233,10 @@ def hs_build_ex(A, B, T_AA, T_AB, T_BB, U, N_A, N_L, N_G, H, S, *, workspace,
     opt.info = _ptr(info)
     opt.mode = int(mode)
     opt.nl_per_atom = p
+    opt.batch = int(batch)
+    tp = _tuning_ptr(tuning)
+    if tp is not None:
+        opt.tuning = tp
     ev = None
     if phase_events is not None:
         if len(phase_events) != HS_NUM_PHASE_EVENTS:
@@ -266,13 +293,17 @@ def hs_ctx_footprint_bytes(ctx, N_G, mode=HS_FP64) -> int:
 
 
 def hs_ctx_build(ctx, A, B, N_G, H, S, *, workspace, stream=None, mode=HS_FP64,
-                 phase_events=None, check=True) -> int:
+                 phase_events=None, batch: int = 0, tuning=None, check=True) -> int:
     _check_c128(A, B, H, S)
     opt = hs_options()
     opt.stream = _stream_handle(stream)
     opt.workspace = _ptr(workspace)
     opt.workspace_bytes = workspace.numel() * workspace.element_size()
     opt.mode = int(mode)
+    opt.batch = int(batch)
+    tp = _tuning_ptr(tuning)
+    if tp is not None:
+        opt.tuning = tp
     ev = None
     if phase_events is not None:
         ev = (ctypes.c_void_p * HS_NUM_PHASE_EVENTS)(*phase_events)
@@ -333,3 +364,30 @@ def hs_server_now(srv) -> float:
 
 def hs_server_destroy(srv) -> None:
     load_library().hs_server_destroy(srv)
+
+
+# ---------------------------------------------------------------------------
+# Batched per-atom stage: tile shapes and the autotuner
+
+
+def hs_tile_config(cfg_id: int):
+    """(BM, BN) of batched tile shape `cfg_id`, or None for an unknown id."""
+    bm, bn = ctypes.c_int(), ctypes.c_int()
+    rc = load_library().hs_tile_config(int(cfg_id), ctypes.byref(bm), ctypes.byref(bn))
+    return None if rc != 0 else (bm.value, bn.value)
+
+
+def hs_autotune_atoms(nl_values, N_G, reps=3, stream=None):
+    """Fastest batched tile shape per N_L on the current device.
+
+    Returns (hs_tuning, ms) with ms[i][c] the minimum time in milliseconds of
+    shape c for nl_values[i]."""
+    vals = np.ascontiguousarray(np.asarray(nl_values, dtype=np.int32).reshape(-1))
+    out = hs_tuning()
+    ms = np.zeros((max(1, vals.size), HS_NUM_TILE_CONFIGS), np.float32)
+    rc = load_library().hs_autotune_atoms(
+        vals.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if vals.size else None,
+        int(vals.size), int(N_G), int(reps), _stream_handle(stream), ctypes.byref(out),
+        ms.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+    _raise(rc, True)
+    return out, ms[: vals.size]

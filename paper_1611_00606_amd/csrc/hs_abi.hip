@@ -127,10 +127,26 @@ size_t AtomPlan::atom_bytes() const {
 }
 
 size_t AtomPlan::kpoint_bytes(int n_g, int mode) const {
-    size_t b = 2 * align_up(16 * (size_t)K * (size_t)n_g);
+    size_t b = 2 * align_up(16 * (size_t)K * (size_t)n_g) + BatchBufs::bytes(n_atoms);
     if (mode == HS_SPLIT_F16)
         b += NSPLIT * (align_up(split_slice_bytes(K, n_g)) + align_up(8 * (size_t)n_g));
     return b;
+}
+
+size_t BatchBufs::bytes(int n_atoms) {
+    return align_up(sizeof(int) * (size_t)n_atoms) + align_up(sizeof(int) * (size_t)(n_atoms + 1)) +
+           align_up(2 * sizeof(int)) + align_up(2 * sizeof(int) * (size_t)n_atoms);
+}
+
+void BatchBufs::carve(int n_atoms, char *base) {
+    size_t o = 0;
+    perm = reinterpret_cast<int *>(base + o);
+    o += align_up(sizeof(int) * (size_t)n_atoms);
+    zoff = reinterpret_cast<int *>(base + o);
+    o += align_up(sizeof(int) * (size_t)(n_atoms + 1));
+    ctrl = reinterpret_cast<int *>(base + o);
+    o += align_up(2 * sizeof(int));
+    flags = reinterpret_cast<int *>(base + o);
 }
 
 void AtomBufs::carve(const AtomPlan &p, char *base) {
@@ -163,6 +179,8 @@ void KpointBufs::carve(const AtomPlan &p, int n_g, int mode, char *base) {
     Z = reinterpret_cast<double2 *>(base);
     W = reinterpret_cast<double2 *>(base + half);
     size_t o = 2 * half;
+    batch.carve(p.n_atoms, base + o);
+    o += BatchBufs::bytes(p.n_atoms);
     for (int i = 0; i < NSPLIT; ++i) {
         sl[i] = nullptr;
         mx[i] = nullptr;
@@ -175,7 +193,8 @@ void KpointBufs::carve(const AtomPlan &p, int n_g, int mode, char *base) {
 }
 
 hipError_t enqueue_atoms(const AtomPlan &p, const AtomBufs &ab, const double2 *T_AA,
-                         const double2 *T_BB, const double2 *U, int *info_out, hipStream_t st) {
+                         const double2 *T_BB, const double2 *U, int *info_out, hipStream_t st,
+                         bool prep) {
     for (int a0 = 0; a0 < p.n_atoms; a0 += TABLE_CHUNK) {
         TableChunk c;
         c.n = std::min(TABLE_CHUNK, p.n_atoms - a0);
@@ -190,6 +209,7 @@ hipError_t enqueue_atoms(const AtomPlan &p, const AtomBufs &ab, const double2 *T
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
+    if (!prep) return hipSuccess;
     return launch_prep(ab.atoms(p), T_AA, T_BB, U, ab.M1, ab.M2, ab.d, ab.sel,
                        info_out ? info_out : ab.info, st);
 }
@@ -197,13 +217,21 @@ hipError_t enqueue_atoms(const AtomPlan &p, const AtomBufs &ab, const double2 *T
 hipError_t enqueue_kpoint(const AtomPlan &p, const AtomBufs &ab, int n_g, int mode,
                           const double2 *A, const double2 *B, const double2 *T_AB,
                           const KpointBufs &kb, double2 *H, double2 *S, hipStream_t st,
-                          const hipEvent_t *ev) {
+                          const hipEvent_t *ev, const AtomStage &stage) {
     hipError_t e;
     auto mark = [&](int i) -> hipError_t {
         return (ev && ev[i]) ? hipEventRecord(ev[i], st) : hipSuccess;
     };
     if ((e = mark(1)) != hipSuccess) return e;
-    e = launch_atom(ab.atoms(p), n_g, A, B, T_AB, ab.M1, ab.M2, kb.Z, kb.W, st);
+    if (stage.batch) {
+        BatchPlan bp;
+        bp.make(p, n_g, stage.cfg);
+        const BatchIO io{stage.T_AA, T_AB, stage.T_BB, stage.U, A, B, ab.M1, ab.M2, ab.d,
+                         ab.sel, stage.info ? stage.info : ab.info, kb.Z, kb.W};
+        e = launch_batch(p, ab.atoms(p), bp, n_g, stage.factor, io, kb.batch, st);
+    } else {
+        e = launch_atom(ab.atoms(p), n_g, A, B, T_AB, ab.M1, ab.M2, kb.Z, kb.W, st);
+    }
     if (e != hipSuccess) return e;
     if ((e = mark(2)) != hipSuccess) return e;
     if (mode == HS_SPLIT_F16) {
@@ -261,7 +289,7 @@ double2 *c2(hs_complex *x) { return reinterpret_cast<double2 *>(x); }
 int run(const hs::AtomPlan &p, int n_g, int mode, const hs_complex *A, const hs_complex *B,
         const hs_complex *T_AA, const hs_complex *T_AB, const hs_complex *T_BB,
         const hs_complex *U, hs_complex *H, hs_complex *S, char *ws, int32_t *info_user,
-        hipStream_t st, void **events) {
+        hipStream_t st, void **events, bool batch = false, const hs_tuning *tuning = nullptr) {
     hipEvent_t ev[HS_NUM_PHASE_EVENTS] = {};
     if (events)
         for (int i = 0; i < HS_NUM_PHASE_EVENTS; ++i) ev[i] = static_cast<hipEvent_t>(events[i]);
@@ -271,9 +299,20 @@ int run(const hs::AtomPlan &p, int n_g, int mode, const hs_complex *A, const hs_
     ab.carve(p, ws);
     hs::KpointBufs kb;
     kb.carve(p, n_g, mode, ws + p.atom_bytes());
-    e = hs::enqueue_atoms(p, ab, c2(T_AA), c2(T_BB), c2(U), info_user, st);
+    e = hs::enqueue_atoms(p, ab, c2(T_AA), c2(T_BB), c2(U), info_user, st, !batch);
     if (e != hipSuccess) return hs::hip_fail(e, "per-atom preparation launch");
-    e = hs::enqueue_kpoint(p, ab, n_g, mode, c2(A), c2(B), c2(T_AB), kb, c2(H), c2(S), st, ev);
+    hs::AtomStage stage;
+    if (batch) {
+        stage.batch = true;
+        stage.factor = true;
+        stage.cfg = tuning ? tuning->cfg : nullptr;
+        stage.T_AA = c2(T_AA);
+        stage.T_BB = c2(T_BB);
+        stage.U = c2(U);
+        stage.info = info_user;
+    }
+    e = hs::enqueue_kpoint(p, ab, n_g, mode, c2(A), c2(B), c2(T_AB), kb, c2(H), c2(S), st, ev,
+                           stage);
     if (e != hipSuccess) return hs::hip_fail(e, "k-point launch");
     return HS_OK;
 }
@@ -295,16 +334,19 @@ int hs_build_ex(const hs_complex *A, const hs_complex *B, const hs_complex *T_AA
     if (!opt) return -12;
     int rc = check_args(A, B, T_AA, T_AB, T_BB, U, N_A, N_L, N_G, H, S, opt->nl_per_atom != nullptr);
     if (rc != HS_OK) return rc;
-    if (!hs::valid_mode(opt->mode)) return -12;
+    if (!hs::valid_mode(opt->mode) || (opt->batch != 0 && opt->batch != 1)) return -12;
     hs::AtomPlan p;
     rc = p.make(N_A, opt->nl_per_atom, N_L);
     if (rc != 0) return rc;
+    if (opt->batch && !hs::BatchPlan::valid(p, opt->tuning ? opt->tuning->cfg : nullptr))
+        return -12;
     rc = hs::check_device();
     if (rc != HS_OK) return rc;
     if (!opt->workspace || opt->workspace_bytes < p.atom_bytes() + p.kpoint_bytes(N_G, opt->mode))
         return HS_ERR_WORKSPACE;
     return run(p, N_G, opt->mode, A, B, T_AA, T_AB, T_BB, U, H, S, static_cast<char *>(opt->workspace),
-               opt->info, static_cast<hipStream_t>(opt->stream), opt->phase_events);
+               opt->info, static_cast<hipStream_t>(opt->stream), opt->phase_events,
+               opt->batch != 0, opt->tuning);
 }
 
 int hs_build(const hs_complex *A, const hs_complex *B, const hs_complex *T_AA,
@@ -332,6 +374,8 @@ int hs_build(const hs_complex *A, const hs_complex *B, const hs_complex *T_AA,
     if (rc == HS_OK && e2 != hipSuccess) rc = hs::hip_fail(e2, "hipFree");
     return rc;
 }
+
+int hs_tile_config(int id, int *bm, int *bn) { return hs::tile_shape(id, bm, bn); }
 
 const char *hs_status_string(int status) {
     const std::string &m = hs::last_error();

@@ -5,8 +5,11 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
+
+#include "../../include/hs_build.h"
 
 namespace hs {
 
@@ -110,23 +113,71 @@ struct AtomBufs {
     Atoms atoms(const AtomPlan &p) const;
 };
 
+// Batched per-atom stage (k_batch.hip): item tables of one launch.
+struct BatchBufs {
+    int *perm;    // [N_A]
+    int *zoff;    // [N_A + 1]
+    int *ctrl;    // [2]
+    int *flags;   // [2 N_A]
+    static size_t bytes(int n_atoms);
+    void carve(int n_atoms, char *base);
+};
+// Host plan: tile shape per N_L, atom order (N_L descending) and the first
+// product tile of each position.
+struct BatchPlan {
+    unsigned char cfg[HS_MAX_NL + 1];
+    std::vector<int> perm, zoff;
+    long long nz = 0;   // product tiles per product (Z or W)
+    // cfg_table: [HS_MAX_NL + 1] tile id per N_L, or NULL for default_tile
+    void make(const AtomPlan &p, int n_g, const unsigned char *cfg_table);
+    // every N_L of the plan maps to an existing tile id
+    static bool valid(const AtomPlan &p, const unsigned char *cfg_table);
+};
+struct BatchIO {
+    const double2 *T_AA, *T_AB, *T_BB, *U, *A, *B;
+    double2 *M1, *M2;
+    double *d;
+    int *sel, *info;
+    double2 *Z, *W;
+};
+int tile_shape(int id, int *bm, int *bn);   // 0, or -1 for an unknown id
+int default_tile(int nl);
+// Persistent launch of the per-atom stage (preparation items only when
+// do_factor) followed, when do_factor, by the wait check.
+hipError_t launch_batch(const AtomPlan &p, const Atoms &at, const BatchPlan &bp, int n_g,
+                        bool do_factor, const BatchIO &io, const BatchBufs &bb, hipStream_t st);
+
 // Per-k-point device buffers.
 constexpr int NSPLIT = 6;   // sliced operands: A, U B, Z, B, P3 (W or A by row), W
 struct KpointBufs {
     double2 *Z, *W;   // [K][N_G] each
     _Float16 *sl[NSPLIT];
     unsigned long long *mx[NSPLIT];
+    BatchBufs batch;
     void carve(const AtomPlan &p, int n_g, int mode, char *base);
 };
 
+// How the per-atom stage of one build runs: separate preparation and product
+// launches (batch = false), or the persistent batched launch with the tile
+// table cfg; factor: the batched launch includes the preparation.
+struct AtomStage {
+    bool batch = false;
+    bool factor = false;
+    const unsigned char *cfg = nullptr;   // [HS_MAX_NL + 1] or NULL
+    const double2 *T_AA = nullptr, *T_BB = nullptr, *U = nullptr;
+    int *info = nullptr;
+};
+
 // Tables, per-atom Cholesky and operand preparation (k-independent).
+// prep = false: tables only (the batched launch prepares the atoms itself).
 hipError_t enqueue_atoms(const AtomPlan &p, const AtomBufs &ab, const double2 *T_AA,
-                         const double2 *T_BB, const double2 *U, int *info_out, hipStream_t st);
+                         const double2 *T_BB, const double2 *U, int *info_out, hipStream_t st,
+                         bool prep = true);
 // Per-atom products and the reductions for one k-point. ev: optional phase
 // events [1..4] as in hs_options.phase_events (ev[0] is recorded by the caller).
 hipError_t enqueue_kpoint(const AtomPlan &p, const AtomBufs &ab, int n_g, int mode,
                           const double2 *A, const double2 *B, const double2 *T_AB,
                           const KpointBufs &kb, double2 *H, double2 *S, hipStream_t st,
-                          const hipEvent_t *ev);
+                          const hipEvent_t *ev, const AtomStage &stage = AtomStage());
 
 }  // namespace hs

@@ -119,7 +119,9 @@ int hs_ctx_build(const hs_ctx *ctx, const hs_complex *A, const hs_complex *B, in
     if (N_G < 1) return -4;
     if (!H) return -5;
     if (!S) return -6;
-    if (!opt || !hs::valid_mode(opt->mode)) return -7;
+    if (!opt || !hs::valid_mode(opt->mode) || (opt->batch != 0 && opt->batch != 1)) return -7;
+    if (opt->batch && !hs::BatchPlan::valid(ctx->plan, opt->tuning ? opt->tuning->cfg : nullptr))
+        return -7;
     if (!opt->workspace || opt->workspace_bytes < ctx->plan.kpoint_bytes(N_G, opt->mode))
         return HS_ERR_WORKSPACE;
     hipStream_t st = static_cast<hipStream_t>(opt->stream);
@@ -131,9 +133,13 @@ int hs_ctx_build(const hs_ctx *ctx, const hs_complex *A, const hs_complex *B, in
     if (ev[0] && (e = hipEventRecord(ev[0], st)) != hipSuccess) return hs::hip_fail(e, "phase event");
     hs::KpointBufs kb;
     kb.carve(ctx->plan, N_G, opt->mode, static_cast<char *>(opt->workspace));
+    hs::AtomStage stage;   // batched: products only, the preparation is cached
+    stage.batch = opt->batch != 0;
+    stage.cfg = opt->tuning ? opt->tuning->cfg : nullptr;
     e = hs::enqueue_kpoint(ctx->plan, ctx->ab, N_G, opt->mode, reinterpret_cast<const double2 *>(A),
                            reinterpret_cast<const double2 *>(B), ctx->T_AB, kb,
-                           reinterpret_cast<double2 *>(H), reinterpret_cast<double2 *>(S), st, ev);
+                           reinterpret_cast<double2 *>(H), reinterpret_cast<double2 *>(S), st, ev,
+                           stage);
     return e == hipSuccess ? HS_OK : hs::hip_fail(e, "hs_ctx_build launch");
 }
 

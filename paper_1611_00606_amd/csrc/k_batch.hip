@@ -1,0 +1,353 @@
+// Batched form of the per-atom stage of Alg. 1 for atoms of mixed N_L: one
+// persistent launch runs every atom's preparation (the Cholesky of T^AA_a
+// with its failure test, prep_atom.h) and every atom's products
+//   Z_a = T_AB,a^H A_a + M2_a^H B_a,   W_a = M1_a^H A_a   (Y_a or X_a)
+// with the tile shape of each atom's products chosen per N_L (a table filled
+// by the autotuner in hs_tune.hip, or the built-in choice below).
+//
+// Work items, taken in order from one atomic counter by a grid of one
+// 8-wave block per CU:
+//   [0, N_A)              preparation of atom perm[i] (atoms by N_L, largest
+//                         first, so the longest factorizations start first)
+//   [N_A, N_A + nz)       Z tiles, atoms in the same order
+//   [N_A + nz, N_A + 2nz) W tiles
+// A Z tile needs M2_a and a W tile needs M1_a; the preparation item of atom a
+// publishes each through a ready flag. An item only ever waits for an item
+// with a smaller index, which some running block has already taken, so every
+// wait ends; the wait is bounded nevertheless, and a wait that runs out is
+// counted and turns every info entry to -1 (checked after the launch).
+// With the preparation done elsewhere (the resident context caches it), the
+// launch has product items only and nothing waits.
+#include "prep_atom.h"
+#include "zmfma_tile.h"
+
+namespace hs {
+
+namespace {
+
+constexpr int BT = 512;   // threads of the persistent block (8 waves)
+
+// Candidate tile shapes (BM rows of the atom's N_L x BN columns of N_G).
+// At most four 16x16 blocks per wave: with the item loop's own state, a
+// larger wave tile does not fit the 256 registers of a two-wave-per-SIMD
+// launch and spills.
+using Cfg0 = TileCfg<32, 128, 16, 1, 8>;
+using Cfg1 = TileCfg<32, 256, 16, 1, 8>;
+using Cfg2 = TileCfg<64, 64, 16, 2, 4>;
+using Cfg3 = TileCfg<64, 128, 16, 2, 4>;
+using Cfg4 = TileCfg<128, 64, 16, 4, 2>;
+using Cfg5 = TileCfg<128, 64, 16, 2, 4>;
+static_assert(Cfg0::NT == BT && Cfg1::NT == BT && Cfg2::NT == BT && Cfg3::NT == BT &&
+                  Cfg4::NT == BT && Cfg5::NT == BT,
+              "every tile shape runs on the whole persistent block");
+static_assert(HS_NUM_TILE_CONFIGS == 6, "tile table and candidate list agree");
+
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int TILE_LDS = 16 * cmax(cmax(cmax(Cfg0::LDS_ELEMS, Cfg1::LDS_ELEMS),
+                                        cmax(Cfg2::LDS_ELEMS, Cfg3::LDS_ELEMS)),
+                                   cmax(Cfg4::LDS_ELEMS, Cfg5::LDS_ELEMS));
+constexpr int BATCH_LDS = cmax(TILE_LDS, PREP_LDS_BYTES);
+static_assert(BATCH_LDS <= 160 * 1024, "LDS of one CU");
+
+constexpr int SPIN_LIMIT = 1 << 22;   // x ~1 us per poll: seconds
+
+struct BatchArgs {
+    Atoms at;
+    const double2 *T_AA, *T_AB, *T_BB, *U, *A, *B;
+    double2 *M1, *M2;
+    double *d;
+    int *sel, *info;
+    double2 *Z, *W;
+    const int *perm;   // [N_A] atom at each position
+    const int *zoff;   // [N_A + 1] first product tile of each position
+    int *ctrl;         // [0] item counter, [1] waits that ran out
+    int *flags;        // [2 N_A] M2 ready, M1 ready
+    int n_g, nz, do_factor;
+    unsigned char cfg[HS_MAX_NL + 1];
+};
+
+template <class C>
+__device__ __forceinline__ void product_tile(int which, int r0, int n, long long t0, int loc,
+                                             int n_g, const double2 *A, const double2 *B,
+                                             const double2 *T_AB, const double2 *M1,
+                                             const double2 *M2, double2 *Z, double2 *W,
+                                             double2 *lds) {
+    const int ct = (n_g + C::BN - 1) / C::BN;
+    const int m0 = (loc / ct) * C::BM;
+    const int n0 = (loc % ct) * C::BN;
+    const double2 *Aa = A + (long long)r0 * n_g;
+    const double2 *Ba = B + (long long)r0 * n_g;
+    Segs<2, false, false> tab;
+    tab.ldp = n;
+    tab.ldq = n_g;
+    tab.len = n;
+    tab.palt = nullptr;
+    tab.sel = nullptr;
+    tab.qscale = nullptr;
+    if (which == 0) {
+        tab.nseg = 2;
+        tab.P[0] = T_AB + t0;
+        tab.Q[0] = Aa;
+        tab.P[1] = M2 + t0;
+        tab.Q[1] = Ba;
+    } else {
+        tab.nseg = 1;
+        tab.P[0] = M1 + t0;
+        tab.Q[0] = Aa;
+        tab.P[1] = M1 + t0;
+        tab.Q[1] = Aa;
+    }
+    Acc<C> acc;
+    ztile_run<C>(tab, m0, n, n0, n_g, acc, lds);
+
+    double2 *out = (which == 0 ? Z : W) + (long long)r0 * n_g;
+#pragma unroll
+    for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+        for (int j = 0; j < C::TN; ++j) {
+            const int g = n0 + acc_col<C>(j);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int l = m0 + acc_row<C>(i, v);
+                if (l < n && g < n_g) out[(long long)l * n_g + g] = double2{acc.re[i][j][v], acc.im[i][j][v]};
+            }
+        }
+}
+
+__device__ __forceinline__ bool wait_flag(const int *f) {
+    for (int i = 0; i < SPIN_LIMIT; ++i) {
+        if (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) return true;
+        __builtin_amdgcn_s_sleep(8);
+    }
+    return false;
+}
+
+__global__ void __launch_bounds__(BT)
+k_batch(BatchArgs args) {
+    __shared__ __align__(16) char lds[BATCH_LDS];
+    __shared__ int s_job[3];   // kind (-1 done, 0 prep, 1 Z, 2 W), atom, tile
+
+    const Atoms at = args.at;
+    const int n_atoms = at.n_atoms;
+    const int nz = args.nz;
+    const int nf = args.do_factor ? n_atoms : 0;
+    const int total = nf + 2 * nz;
+
+    for (;;) {
+        __syncthreads();   // the previous item is done with LDS and s_job
+        if (threadIdx.x == 0) {
+            const int it = atomicAdd(args.ctrl, 1);
+            int kind = -1, atom = 0, loc = 0;
+            if (it < nf) {
+                kind = 0;
+                atom = args.perm[it];
+            } else if (it < total) {
+                int j = it - nf;
+                kind = 1;
+                if (j >= nz) {
+                    kind = 2;
+                    j -= nz;
+                }
+                int lo = 0, hi = n_atoms - 1;   // last position with zoff <= j
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (args.zoff[mid] <= j) lo = mid;
+                    else hi = mid - 1;
+                }
+                atom = args.perm[lo];
+                loc = j - args.zoff[lo];
+                if (args.do_factor &&
+                    !wait_flag(args.flags + (kind == 1 ? atom : n_atoms + atom))) {
+                    atomicAdd(args.ctrl + 1, 1);
+                    kind = 3;   // skipped
+                }
+            }
+            s_job[0] = kind;
+            s_job[1] = atom;
+            s_job[2] = loc;
+        }
+        __syncthreads();
+        const int kind = s_job[0], atom = s_job[1], loc = s_job[2];
+        if (kind < 0) break;
+        if (kind == 3) continue;
+        if (kind == 0) {
+            prep_atom<BT>(at, atom, args.T_AA, args.T_BB, args.U, args.M1, args.M2, args.d,
+                          args.sel, args.info, lds, args.flags + atom,
+                          args.flags + n_atoms + atom);
+            continue;
+        }
+        if (args.do_factor)   // every wave acquires what the preparation published
+            (void)__hip_atomic_load(args.flags + (kind == 1 ? atom : n_atoms + atom),
+                                    __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const int r0 = at.row_off[atom];
+        const int n = at.row_off[atom + 1] - r0;
+        const long long t0 = at.t_off[atom];
+        const int which = kind - 1;
+        double2 *tl = reinterpret_cast<double2 *>(lds);
+        switch (args.cfg[n]) {
+            case 0:
+                product_tile<Cfg0>(which, r0, n, t0, loc, args.n_g, args.A, args.B, args.T_AB,
+                                   args.M1, args.M2, args.Z, args.W, tl);
+                break;
+            case 1:
+                product_tile<Cfg1>(which, r0, n, t0, loc, args.n_g, args.A, args.B, args.T_AB,
+                                   args.M1, args.M2, args.Z, args.W, tl);
+                break;
+            case 2:
+                product_tile<Cfg2>(which, r0, n, t0, loc, args.n_g, args.A, args.B, args.T_AB,
+                                   args.M1, args.M2, args.Z, args.W, tl);
+                break;
+            case 3:
+                product_tile<Cfg3>(which, r0, n, t0, loc, args.n_g, args.A, args.B, args.T_AB,
+                                   args.M1, args.M2, args.Z, args.W, tl);
+                break;
+            case 4:
+                product_tile<Cfg4>(which, r0, n, t0, loc, args.n_g, args.A, args.B, args.T_AB,
+                                   args.M1, args.M2, args.Z, args.W, tl);
+                break;
+            default:
+                product_tile<Cfg5>(which, r0, n, t0, loc, args.n_g, args.A, args.B, args.T_AB,
+                                   args.M1, args.M2, args.Z, args.W, tl);
+                break;
+        }
+    }
+}
+
+// Item tables of one launch, written from kernel arguments (no host copy):
+// a chunk of up to BT_CHUNK positions per launch; also clears the counter
+// and the ready flags of the chunk's atoms.
+constexpr int BT_CHUNK = 256;
+struct BatchChunk {
+    int perm[BT_CHUNK];
+    int zoff[BT_CHUNK];
+    int p0, n, last, n_atoms, nz;
+};
+
+__global__ void __launch_bounds__(256)
+k_batch_tables(BatchChunk c, int *perm, int *zoff, int *ctrl, int *flags) {
+    for (int i = threadIdx.x; i < c.n; i += blockDim.x) {
+        perm[c.p0 + i] = c.perm[i];
+        zoff[c.p0 + i] = c.zoff[i];
+        flags[c.perm[i]] = 0;
+        flags[c.n_atoms + c.perm[i]] = 0;
+    }
+    if (threadIdx.x == 0 && c.p0 == 0) {
+        ctrl[0] = 0;
+        ctrl[1] = 0;
+    }
+    if (threadIdx.x == 0 && c.last) zoff[c.n_atoms] = c.nz;
+}
+
+// After a launch with preparation items: a wait that ran out marks the build.
+__global__ void __launch_bounds__(256) k_batch_check(const int *ctrl, int *info, int n_atoms) {
+    if (ctrl[1] == 0) return;
+    for (int a = blockIdx.x * 256 + threadIdx.x; a < n_atoms; a += gridDim.x * 256) info[a] = -1;
+}
+
+int num_cus() {
+    static int cached[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cached[dev]) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            n < 1)
+            n = 256;
+        cached[dev] = n;
+    }
+    return cached[dev];
+}
+
+}  // namespace
+
+int tile_shape(int id, int *bm, int *bn) {
+    static const int shapes[HS_NUM_TILE_CONFIGS][2] = {
+        {Cfg0::BM, Cfg0::BN}, {Cfg1::BM, Cfg1::BN}, {Cfg2::BM, Cfg2::BN},
+        {Cfg3::BM, Cfg3::BN}, {Cfg4::BM, Cfg4::BN}, {Cfg5::BM, Cfg5::BN}};
+    if (id < 0 || id >= HS_NUM_TILE_CONFIGS) return -1;
+    if (bm) *bm = shapes[id][0];
+    if (bn) *bn = shapes[id][1];
+    return 0;
+}
+
+int default_tile(int nl) { return nl <= 32 ? 1 : nl <= 64 ? 3 : 4; }
+
+void BatchPlan::make(const AtomPlan &p, int n_g, const unsigned char *cfg_table) {
+    for (int v = 0; v <= HS_MAX_NL; ++v) cfg[v] = cfg_table ? cfg_table[v] : (unsigned char)default_tile(v);
+    perm.resize(p.n_atoms);
+    for (int a = 0; a < p.n_atoms; ++a) perm[a] = a;
+    std::stable_sort(perm.begin(), perm.end(),
+                     [&](int x, int y) { return p.nl[x] > p.nl[y]; });
+    zoff.assign(p.n_atoms + 1, 0);
+    long long acc = 0;
+    for (int i = 0; i < p.n_atoms; ++i) {
+        zoff[i] = (int)acc;
+        const int n = p.nl[perm[i]];
+        int bm = 0, bn = 0;
+        tile_shape(cfg[n], &bm, &bn);
+        acc += (long long)((n + bm - 1) / bm) * ((n_g + bn - 1) / bn);
+    }
+    zoff[p.n_atoms] = (int)acc;
+    nz = acc;
+}
+
+bool BatchPlan::valid(const AtomPlan &p, const unsigned char *cfg_table) {
+    if (!cfg_table) return true;
+    for (int a = 0; a < p.n_atoms; ++a)
+        if (cfg_table[p.nl[a]] >= HS_NUM_TILE_CONFIGS) return false;
+    return true;
+}
+
+hipError_t launch_batch(const AtomPlan &p, const Atoms &at, const BatchPlan &bp, int n_g,
+                        bool do_factor, const BatchIO &io, const BatchBufs &bb, hipStream_t st) {
+    if (bp.nz > (1LL << 30)) return hipErrorInvalidValue;
+    for (int p0 = 0; p0 < p.n_atoms; p0 += BT_CHUNK) {
+        BatchChunk c;
+        c.p0 = p0;
+        c.n = std::min(BT_CHUNK, p.n_atoms - p0);
+        for (int i = 0; i < c.n; ++i) {
+            c.perm[i] = bp.perm[p0 + i];
+            c.zoff[i] = bp.zoff[p0 + i];
+        }
+        c.last = p0 + c.n == p.n_atoms;
+        c.n_atoms = p.n_atoms;
+        c.nz = (int)bp.nz;
+        hipLaunchKernelGGL(k_batch_tables, dim3(1), dim3(256), 0, st, c, bb.perm, bb.zoff, bb.ctrl,
+                           bb.flags);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    BatchArgs a;
+    a.at = at;
+    a.T_AA = io.T_AA;
+    a.T_AB = io.T_AB;
+    a.T_BB = io.T_BB;
+    a.U = io.U;
+    a.A = io.A;
+    a.B = io.B;
+    a.M1 = io.M1;
+    a.M2 = io.M2;
+    a.d = io.d;
+    a.sel = io.sel;
+    a.info = io.info;
+    a.Z = io.Z;
+    a.W = io.W;
+    a.perm = bb.perm;
+    a.zoff = bb.zoff;
+    a.ctrl = bb.ctrl;
+    a.flags = bb.flags;
+    a.n_g = n_g;
+    a.nz = (int)bp.nz;
+    a.do_factor = do_factor ? 1 : 0;
+    for (int v = 0; v <= HS_MAX_NL; ++v) a.cfg[v] = bp.cfg[v];
+    const long long items = (do_factor ? p.n_atoms : 0) + 2 * bp.nz;
+    const int grid = (int)std::min<long long>(num_cus(), items);
+    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(BT), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !do_factor) return e;
+    hipLaunchKernelGGL(k_batch_check, dim3((p.n_atoms + 255) / 256), dim3(256), 0, st, bb.ctrl,
+                       io.info, p.n_atoms);
+    return hipGetLastError();
+}
+
+}  // namespace hs

@@ -71,10 +71,11 @@ struct TileCfg {
     static_assert(BM % (16 * WM) == 0 && BN % (16 * WN) == 0, "wave tiling");
     static_assert(NT % BM == 0 && NT % BN == 0, "loader needs NT multiple of BM, BN");
     static_assert(BK % RPP == 0 && BK % RPQ == 0 && BK % 4 == 0, "stage depth");
-    // With BM, BN multiples of the 64-lane wave, every row a thread loads is
-    // the same for its whole wave, so the row bookkeeping runs on the scalar
-    // unit (see ztile_run).
-    static_assert(BM % 64 == 0 && BN % 64 == 0, "wave-uniform loader rows");
+    static_assert(BM % 16 == 0 && BN % 16 == 0, "16-wide MFMA blocks");
+    // With BM (BN) a multiple of the 64-lane wave, every P (Q) row a thread
+    // loads is the same for its whole wave, so that row bookkeeping runs on
+    // the scalar unit (see ztile_run); narrower tiles keep it per lane.
+    static constexpr bool PUNI = BM % 64 == 0, QUNI = BN % 64 == 0;
 };
 
 template <class C>
@@ -132,13 +133,14 @@ __device__ __forceinline__ void ztile_run(const Segs<NSEG, SEL, SCALE> &t, int m
     if (nst == 0) return;
 
     // loader coordinates: fixed column per thread, rows strided by RPP / RPQ;
-    // out-of-range columns are clamped for the load and zeroed at the store
-    // tid / BM is uniform across a wave (BM is a multiple of 64): declaring it
-    // so moves segment lookup, row pointers and metadata loads to SGPRs/SALU.
+    // out-of-range columns are clamped for the load and zeroed at the store.
+    // When BM is a multiple of 64, tid / BM is uniform across a wave:
+    // declaring it so moves segment lookup, row pointers and metadata loads
+    // to SGPRs/SALU.
     const int pc = tid % C::BM;
-    const int pr0 = __builtin_amdgcn_readfirstlane(tid / C::BM);
+    const int pr0 = C::PUNI ? __builtin_amdgcn_readfirstlane(tid / C::BM) : tid / C::BM;
     const int qc = tid % C::BN;
-    const int qr0 = __builtin_amdgcn_readfirstlane(tid / C::BN);
+    const int qr0 = C::QUNI ? __builtin_amdgcn_readfirstlane(tid / C::BN) : tid / C::BN;
     const bool pcol_ok = (m0 + pc) < mlim;
     const bool qcol_ok = (n0 + qc) < nlim;
     const int pcol = pcol_ok ? m0 + pc : mlim - 1;

@@ -12,7 +12,8 @@ from ._binding import HS_FP64, hs_build_ex, hs_workspace_bytes
 
 
 class DeviceBuild:
-    def __init__(self, A, B, T_AA, T_AB, T_BB, U, nl, n_g, device="cuda:0", mode=HS_FP64):
+    def __init__(self, A, B, T_AA, T_AB, T_BB, U, nl, n_g, device="cuda:0", mode=HS_FP64,
+                 batch=0, tuning=None):
         import torch
         self.device = torch.device(device)
         nl = np.asarray(nl, dtype=np.int32)
@@ -22,6 +23,8 @@ class DeviceBuild:
         self.N_L = int(nl[0]) if self.uniform else int(nl.max())
         self.nl_per_atom = None if self.uniform else nl
         self.mode = mode
+        self.batch = int(batch)
+        self.tuning = tuning
 
         def up(x):
             return torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex128)).to(self.device)
@@ -46,7 +49,7 @@ class DeviceBuild:
                            self.N_A, self.N_L, self.N_G, self.H, self.S,
                            workspace=self.workspace, info=self.info, stream=stream,
                            mode=self.mode, nl_per_atom=self.nl_per_atom,
-                           phase_events=phase_events)
+                           phase_events=phase_events, batch=self.batch, tuning=self.tuning)
 
     def results(self):
         """(H, S, info) as host numpy arrays (synchronizes)."""

@@ -50,9 +50,9 @@ class Context:
         return B.hs_ctx_workspace_bytes(self.handle, n_g, mode)
 
     def build(self, A, Bm, n_g, H, S, workspace, stream=None, phase_events=None,
-              mode: int = B.HS_FP64):
+              mode: int = B.HS_FP64, batch: int = 0, tuning=None):
         return B.hs_ctx_build(self.handle, A, Bm, n_g, H, S, workspace=workspace, stream=stream,
-                              phase_events=phase_events, mode=mode)
+                              phase_events=phase_events, mode=mode, batch=batch, tuning=tuning)
 
     def close(self):
         if self.handle:

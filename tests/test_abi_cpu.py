@@ -148,3 +148,52 @@ def test_split_mode_workspace():
     groups = (K + 15) // 16 * 4
     assert split >= fp64 + 6 * 4 * groups * 1000 * 16
     assert P.hs_workspace_bytes(10, None, 49, 1000, 2) == 0
+
+
+def test_tile_configs():
+    shapes = [P.hs_tile_config(c) for c in range(P.HS_NUM_TILE_CONFIGS)]
+    assert all(s is not None for s in shapes)
+    for bm, bn in shapes:
+        assert bm % 16 == 0 and bn % 16 == 0 and bm * bn <= 8192
+    assert P.hs_tile_config(-1) is None and P.hs_tile_config(P.HS_NUM_TILE_CONFIGS) is None
+    from paper_1611_00606_amd.tuning import default_shape, tuning_from_table
+    assert all(0 <= default_shape(v) < P.HS_NUM_TILE_CONFIGS for v in range(1, 129))
+    t = tuning_from_table({16: 0, 121: 5})
+    assert t.cfg[16] == 0 and t.cfg[121] == 5 and t.cfg[49] == default_shape(49)
+    with pytest.raises(ValueError):
+        tuning_from_table({16: 6})
+    with pytest.raises(ValueError):
+        tuning_from_table({0: 1})
+
+
+def test_batch_option_checks():
+    lib = P.load_library()
+    opt = Bd.hs_options()
+    opt.batch = 2
+    assert lib.hs_build_ex(*[FAKE] * 6, 2, 4, 8, FAKE, FAKE, ctypes.byref(opt)) == -12
+    opt = Bd.hs_options()
+    opt.batch = 1
+    t = Bd.hs_tuning()
+    for v in range(len(t.cfg)):
+        t.cfg[v] = 1
+    t.cfg[4] = 6   # the N_L in use maps to an unknown shape
+    opt.tuning = ctypes.pointer(t)
+    assert lib.hs_build_ex(*[FAKE] * 6, 2, 4, 8, FAKE, FAKE, ctypes.byref(opt)) == -12
+    opt = Bd.hs_options()
+    opt.batch = 2
+    assert lib.hs_ctx_build(FAKE, FAKE, FAKE, 8, FAKE, FAKE, ctypes.byref(opt)) == -7
+
+
+def test_autotune_argument_checks():
+    lib = P.load_library()
+    t = Bd.hs_tuning()
+    vals = np.array([16, 49], np.int32)
+    vp = vals.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    assert lib.hs_autotune_atoms(None, 2, 100, 1, None, ctypes.byref(t), None) == -1
+    assert lib.hs_autotune_atoms(vp, 0, 100, 1, None, ctypes.byref(t), None) == -2
+    bad = np.array([16, 129], np.int32)
+    assert lib.hs_autotune_atoms(bad.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 2, 100, 1,
+                                 None, ctypes.byref(t), None) == -2
+    assert lib.hs_autotune_atoms(vp, 2, 0, 1, None, ctypes.byref(t), None) == -3
+    assert lib.hs_autotune_atoms(vp, 2, 100, 0, None, ctypes.byref(t), None) == -4
+    assert lib.hs_autotune_atoms(vp, 2, 100, 1, None, None, None) == -6
