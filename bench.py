@@ -29,7 +29,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
+FP16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense FP16 matrix peak
 HBM_PEAK_GBS = 8000.0
+# FP16 MFMA flops the split form issues per FP64 flop of the reductions: per
+# complex multiply-add (8 FP64 flops) 10 slice pairs x 2 MFMAs (Re, Im) x 2
+# interleaved real products x 2 flops = 80.
+SPLIT_F16_PER_FP64 = 10.0
 
 
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_reduce_precision_ng8000.md")
@@ -147,7 +152,7 @@ def split_bench(p, steps: int, warmup: int, fp64_ms: float, hip, n_cols: int = 1
     import torch
     import oracle
     from paper_1611_00606_amd import HS_SPLIT_F16, DeviceBuild
-    from paper_1611_00606_amd.flops import algorithmic_flops
+    from paper_1611_00606_amd.flops import algorithmic_flops, reduction_flops
 
     run = DeviceBuild.from_problem(p, device="cuda:0", mode=HS_SPLIT_F16)
     ph, total = timed_builds(run, steps, warmup, hip)
@@ -163,16 +168,68 @@ def split_bench(p, steps: int, warmup: int, fp64_ms: float, hip, n_cols: int = 1
     Sr = oracle.overlap_columns(p.A, p.B, p.U, p.nl, cols)
     f = algorithmic_flops(p.nl, p.N_G, info)
     return {
-        "mode": "split_f16 (4 x 9-bit slices, FP16 MFMA, FP32 accumulation, FP64 recombination)",
+        "mode": "split_f16 (slices of 8+9+9+9 bits in FP16, 10 slice pairs on FP16 MFMA, FP32 "
+                "accumulation flushed every 64 rows, FP64 recombination)",
         "ms_per_step": round(total, 3),
         "value": round(f / (total * 1e-3) / 1e12, 3),
         "unit": "TFLOP/s (FP64-equivalent)",
         "speedup_vs_fp64": round(fp64_ms / total, 3),
         "phases_ms": {"prep_cholesky": round(float(ph[0]), 4), "atom_products": round(float(ph[1]), 4),
                       "slice_and_reduce_HS": round(float(ph[2]), 4), "mirror": round(float(ph[3]), 4)},
+        "roofline": {
+            "kernel": "k_slice + k_split_reduce (phase 2..3)",
+            "bound": "mfma",
+            "achieved": round(SPLIT_F16_PER_FP64 * reduction_flops(p.nl, p.N_G) / (ph[2] * 1e-3) / 1e12, 2),
+            "peak": FP16_MFMA_PEAK_TFLOPS,
+            "unit": "TFLOP/s (FP16 MFMA flops issued)",
+            "frac": round(SPLIT_F16_PER_FP64 * reduction_flops(p.nl, p.N_G) / (ph[2] * 1e-3) / 1e12
+                          / FP16_MFMA_PEAK_TFLOPS, 4),
+        },
         "rel_err_H": float(np.linalg.norm(Hc - Hr) / np.linalg.norm(Hr)),
         "rel_err_S": float(np.linalg.norm(Sc - Sr) / np.linalg.norm(Sr)),
         "err_sample": f"{len(cols)} seeded columns of H and S vs the CPU oracle",
+    }
+
+
+def batching_bench(seed: int, steps: int, hip):
+    """Batched form on the mixed-N_L workload (128 atoms, N_L 16/49/81/121 x 32,
+    N_G = 6000, 6 failing atoms): per-atom stage (preparation + products) and
+    whole build with separate launches, with the batched launch on the
+    built-in tile shapes, and with the shapes the autotuner picks."""
+    import torch
+    from hs_inputs import make_config
+    from paper_1611_00606_amd import DeviceBuild
+    from paper_1611_00606_amd.flops import paper_line_flops
+    from paper_1611_00606_amd.tuning import autotune
+
+    p = make_config("batching", seed=seed)
+    t0 = time.perf_counter()
+    tuning, report = autotune(sorted(set(p.nl.tolist())), p.N_G, reps=3)
+    tune_s = time.perf_counter() - t0
+    res, info = {}, None
+    for name, kw in (("separate", {}), ("batched_default", {"batch": 1}),
+                     ("batched_tuned", {"batch": 1, "tuning": tuning})):
+        run = DeviceBuild.from_problem(p, device="cuda:0", **kw)
+        ph, total = timed_builds(run, steps, 1, hip)
+        info = run.info.cpu().numpy()
+        res[name] = (float(ph[0] + ph[1]), total)
+        del run
+        torch.cuda.empty_cache()
+    f = paper_line_flops(p.nl, p.N_G, info)
+    f_atoms = sum(f[k] for k in ("5", "6", "19", "21", "24"))
+    return {
+        "workload": f"batching: N_A={p.N_A}, N_L 16/49/81/121 x 32, N_G={p.N_G}, "
+                    f"{int((info != 0).sum())} failing atoms",
+        "atom_stage_ms": {k: round(v[0], 4) for k, v in res.items()},
+        "build_ms": {k: round(v[1], 3) for k, v in res.items()},
+        "atom_stage_tflops": {k: round(f_atoms / (v[0] * 1e-3) / 1e12, 3) for k, v in res.items()},
+        "speedup_atom_stage_tuned_vs_separate": round(res["separate"][0] / res["batched_tuned"][0], 3),
+        "atom_stage_frac_of_fp64_peak": round(f_atoms / (res["batched_tuned"][0] * 1e-3) / 1e12
+                                              / FP64_MFMA_PEAK_TFLOPS, 4),
+        "autotune": {str(v): {"bm_bn": list(r["bm_bn"]), "ms_per_shape": r["ms"]}
+                     for v, r in report.items()},
+        "autotune_s": round(tune_s, 2),
+        "atom_stage_flops": f_atoms,
     }
 
 
@@ -264,6 +321,8 @@ def main():
                     help="skip the serving-form measurement (k-point builds/s, p50/p99)")
     ap.add_argument("--no-split", action="store_true",
                     help="skip the split-precision measurement")
+    ap.add_argument("--no-batching", action="store_true",
+                    help="skip the batched per-atom stage measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run one plain device copy of MIB MiB (to scale HBM byte "
                          "counters against a kernel of known traffic) and exit")
@@ -373,6 +432,9 @@ def main():
         print("bench: split precision", file=sys.stderr, flush=True)
         hip = HipEvents()
         out["split"] = split_bench(p, max(3, args.steps // 2), 1, ms_step, hip)
+    if not args.no_batching:
+        print("bench: batched per-atom stage", file=sys.stderr, flush=True)
+        out["batching"] = batching_bench(args.seed, max(3, args.steps // 2), HipEvents())
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
     if not args.no_serving:

@@ -7,11 +7,14 @@
 // Slicing (error-free): for each operand column n let e[n] be the exponent
 // with max_k max(|Re X[k][n]|, |Im X[k][n]|) < 2^e[n]. The scaled values
 // x = X 2^-e lie in (-1, 1) and are written exactly as
-//     x = sum_{s=1..NSL} sig_s 2^(-b s) + r,   |r| <= 2^-(b NSL + 1),
-// with b = SBITS bits per slice: sig_1 = rint(2^b x) in [-2^b, 2^b] and
-// sig_s = rint(2^b r_{s-1}) in [-2^(b-1), 2^(b-1)] (r_s the running
-// remainder; every step is exact in FP64). With b <= 10 every sig_s is an
-// integer that FP16 holds exactly.
+//     x = sig_1 2^-b1 + sum_{s=2..NSL} sig_s 2^-(b1 + b (s-1)) + r
+// with b1 bits in the first slice and b bits in the others:
+// sig_1 = rint(2^b1 x) in [-2^b1, 2^b1], then sig_s = rint(2^b r_{s-1}) in
+// [-2^(b-1), 2^(b-1)] (r_s the running remainder, |r_NSL| <=
+// 2^-(b1 + b (NSL-1) + 1); every step is exact in FP64). With b1, b <= 10
+// every sig_s is an integer that FP16 holds exactly. The weight of a pair
+// (s, t) is 2^-(2 b1 + b (s + t - 2)): it depends on s + t only, so pairs of
+// one level c = s + t share an accumulator.
 //
 // Complex products without extra passes: along the contraction index the real
 // and imaginary parts are interleaved, P' = (p_re, p_im), Q'_re = (q_re, q_im)
@@ -22,17 +25,17 @@
 // Accumulation: the slice pairs (s, t) with s + t <= NSL + 1 are summed into
 // one FP32 accumulator per level c = s + t and, every FLUSH stages (16
 // complex rows each) and at the end of each (P, Q) segment, combined in FP64:
-//     acc += 2^(eP[m] + eQ[n] - 2b) (L_2 + 2^-b L_3 + 2^-2b L_4 + ...)
-// and cleared. Default scheme (b = 9, NSL = 4, FLUSH = 2, i.e. 32 rows =
-// 64 real products per pair between flushes):
-//   level 2: |sig_1 sig_1| <= 2^18, sum <= 64 * 2^18 = 2^24: exact;
-//   level 3: two pairs <= 2^17 each, sum <= 2^24: exact;
+//     acc += 2^(eP[m] + eQ[n] - 2 b1) (L_2 + 2^-b L_3 + 2^-2b L_4 + ...)
+// and cleared. Default scheme (b1 = 8, b = 9, NSL = 4, FLUSH = 4, i.e. 64
+// rows = 128 real products per pair between flushes):
+//   level 2: |sig_1 sig_1| <= 2^16, sum <= 2^7 * 2^16 = 2^23: exact;
+//   level 3: two pairs <= 2^8 * 2^8 each, sum <= 2^24: exact;
 //   levels 4, 5 (weights 2^-18, 2^-27 relative to level 2) may round, at
 //   2^-24 of their own size, i.e. below 2^-42 of the leading terms.
 // Products of FP16 integers are exact in FP32 and, within one MFMA, partial
 // sums of a level stay below 2^24, so the MFMA's internal order is immaterial.
-// Errors left: the remainders (2^-37 of the column maxima), the dropped pairs
-// (s + t > 5, at most 2^-38), and FP64 rounding; relative to a typical
+// Errors left: the remainders (2^-36 of the column maxima), the dropped pairs
+// (s + t > 5, at most 2^-37), and FP64 rounding; relative to a typical
 // product (entries a few standard deviations below their column maximum)
 // about 2^-32.
 #include "hs_internal.h"
@@ -41,11 +44,14 @@
 #ifndef HS_SPLIT_NSL
 #define HS_SPLIT_NSL 4
 #endif
+#ifndef HS_SPLIT_BITS1
+#define HS_SPLIT_BITS1 8
+#endif
 #ifndef HS_SPLIT_BITS
 #define HS_SPLIT_BITS 9
 #endif
 #ifndef HS_SPLIT_FLUSH
-#define HS_SPLIT_FLUSH 2
+#define HS_SPLIT_FLUSH 4
 #endif
 #ifndef HS_SPLIT_WM
 #define HS_SPLIT_WM 4
@@ -62,9 +68,10 @@ typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int NSL = HS_SPLIT_NSL;      // slices per value
-constexpr int SBITS = HS_SPLIT_BITS;   // bits per slice
+constexpr int SBITS1 = HS_SPLIT_BITS1; // bits of the first slice
+constexpr int SBITS = HS_SPLIT_BITS;   // bits of the other slices
 constexpr int NLEV = NSL;              // levels c = 2 .. NSL + 1
-static_assert(SBITS <= 10, "slices must be integers FP16 holds exactly");
+static_assert(SBITS1 <= 10 && SBITS <= 10, "slices must be integers FP16 holds exactly");
 
 // ---------------------------------------------------------------------------
 // Column maxima. A positive double's bit pattern orders like the double, so
@@ -150,7 +157,7 @@ k_slice(SliceSrc src, int K, int n_g, int groups) {
         h8 h;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const double t = x[j] * (double)(1 << SBITS);
+            const double t = x[j] * (double)(1 << (s == 0 ? SBITS1 : SBITS));
             const double sig = rint(t);
             x[j] = t - sig;
             h[j] = (_Float16)sig;
@@ -171,6 +178,13 @@ constexpr int STM = SWTM / 16;          // 16-row blocks per wave
 constexpr int STN = SWTN / 16;          // 16-col blocks per wave
 constexpr int SGRP = 4;                 // groups (of 4 complex rows) per stage = 16 rows
 constexpr int FLUSH = HS_SPLIT_FLUSH;   // stages per flush
+// exactness of the two leading levels between flushes (2 * 16 * FLUSH real
+// products per pair): level 2 one pair of |sig_1| <= 2^b1, level 3 two
+// pairs of |sig_1| <= 2^b1 times |sig_2| <= 2^(b-1)
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
+static_assert((32 * FLUSH) == (1 << ilog2(32 * FLUSH)), "FLUSH is a power of two");
+static_assert(2 * SBITS1 + ilog2(32 * FLUSH) <= 24, "level 2 exact in FP32");
+static_assert(SBITS1 + SBITS - 1 + 1 + ilog2(32 * FLUSH) <= 24, "level 3 exact in FP32");
 constexpr int SBAND = 8;
 // LDS per operand per stage: NSL slices x SGRP groups x 64 columns x 16 B
 constexpr int LDS_OP = NSL * SGRP * 64;   // in units of 16 B
@@ -283,14 +297,14 @@ __device__ __forceinline__ void split_segment(const SplitSeg sg, int n_g, int gr
     };
 
     // column scales of this lane's accumulator rows (g') and columns (g),
-    // with the 2^-2b weight of the first level folded in
+    // with the 2^-2b1 weight of the first level folded in
     double sP[STM][4], sQ[STN];
 #pragma unroll
     for (int i = 0; i < STM; ++i)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int m = m0 + wm * SWTM + i * 16 + 4 * (lane >> 4) + v;
-            sP[i][v] = ldexp(1.0, col_exp(sg.mP, m < n_g ? m : n_g - 1) - 2 * SBITS);
+            sP[i][v] = ldexp(1.0, col_exp(sg.mP, m < n_g ? m : n_g - 1) - 2 * SBITS1);
         }
 #pragma unroll
     for (int j = 0; j < STN; ++j) {
