@@ -199,7 +199,7 @@ def batching_bench(seed: int, steps: int, hip):
     import torch
     from hs_inputs import make_config
     from paper_1611_00606_amd import DeviceBuild
-    from paper_1611_00606_amd.flops import paper_line_flops
+    from paper_1611_00606_amd.flops import paper_step_flops
     from paper_1611_00606_amd.tuning import autotune
 
     p = make_config("batching", seed=seed)
@@ -215,8 +215,9 @@ def batching_bench(seed: int, steps: int, hip):
         res[name] = (float(ph[0] + ph[1]), total)
         del run
         torch.cuda.empty_cache()
-    f = paper_line_flops(p.nl, p.N_G, info)
-    f_atoms = sum(f[k] for k in ("5", "6", "19", "21", "24"))
+    f = paper_step_flops(p.nl, p.N_G, info)
+    f_atoms = sum(f[k] for k in ("loop1_zgemm_TBA_A", "loop1_zhemm_TBB_B", "loop2_zpotrf",
+                                 "loop2_ztrmm_Y", "loop2_zhemm_X"))
     return {
         "workload": f"batching: N_A={p.N_A}, N_L 16/49/81/121 x 32, N_G={p.N_G}, "
                     f"{int((info != 0).sum())} failing atoms",

@@ -44,8 +44,8 @@ hipError_t launch_atom(const Atoms &at, int n_g, const double2 *A, const double2
                        const double2 *T_AB, const double2 *M1, const double2 *M2,
                        double2 *Z, double2 *W, hipStream_t st);
 
-// Large reductions (Alg. 1 l.10, 13-15, 28-29) into the lower triangles of
-// H and S (complex FP64 MFMA).
+// Large reductions (Alg. 1's zher2k, zherk pair of S, failure-branch zgemm
+// and HPD zherk) into the lower triangles of H and S (complex FP64 MFMA).
 hipError_t launch_reduce(int K, int n_g, const double2 *A, const double2 *B,
                          const double2 *Z, const double2 *W, const int *sel,
                          const double *d, double2 *H, double2 *S, hipStream_t st);

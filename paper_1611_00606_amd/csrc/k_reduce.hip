@@ -1,8 +1,8 @@
 // The large stacked reductions of Alg. 1, on complex FP64 MFMA tiles:
-//   H = Z^H B + B^H Z              (l.10, zher2k)
-//     + A_notHPD^H X_notHPD        (l.28, zgemm)
-//     + Y_HPD^H Y_HPD              (l.29, zherk)
-//   S = A^H A + (U B)^H (U B)      (l.13-15, zherk, scaling, zherk)
+//   H = Z^H B + B^H Z              (zher2k)
+//     + A_notHPD^H X_notHPD        (failure-branch zgemm)
+//     + Y_HPD^H Y_HPD              (HPD zherk)
+//   S = A^H A + (U B)^H (U B)      (zherk, scaling of B by U, zherk)
 // The second-loop operands are held in one stacked matrix W (Y_a or X_a in
 // atom a's rows); for the rows of failing atoms the left operand is A, chosen
 // per row by `sel`, so no compaction of the stacks is needed. The U scaling

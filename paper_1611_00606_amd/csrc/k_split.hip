@@ -1,5 +1,6 @@
 // Split-precision form of the large reductions (the five stacked products of
-// Alg. 1, l.10, 13-15, 28-29): FP64 operands are cut into FP16 slices, the
+// Alg. 1: zher2k, the two zherk of S, the failure-branch zgemm and the HPD
+// zherk): FP64 operands are cut into FP16 slices, the
 // slice products run on FP16 MFMA with FP32 accumulation, and the slices are
 // recombined in FP64. The per-atom Cholesky, the HPD test and the per-atom
 // products stay in FP64 (they produce the Z, W operands sliced here).

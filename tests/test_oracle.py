@@ -230,7 +230,8 @@ def test_algorithm1_equals_definition(case, mid):
 
 
 def test_atom_products_against_algorithm_steps(mid):
-    """Z, Y/X from their definitions; their stacked products rebuild H (Alg. 1 l.10, 28, 29)."""
+    """Z, Y/X from their definitions; their stacked products rebuild H (Alg. 1's zher2k,
+    failure-branch zgemm and HPD zherk)."""
     p = mid
     Z, W, info = O.atom_products(p.A, p.B, p.T_AA, p.T_AB, p.T_BB, p.nl)
     assert sorted(np.nonzero(info)[0].tolist()) == p.failing
@@ -291,9 +292,10 @@ def test_cholesky_shift_and_nan():
 
 # P14: the flop formulas of Alg. 1 reproduce the paper's Tab. 6 rates.
 def test_flop_formulas_reproduce_table6():
-    from paper_1611_00606_amd.flops import paper_line_flops
-    f = paper_line_flops(np.full(512, 49), 9273, np.zeros(512, int))
-    want = {"loop1": f["5"] + f["6"], "S1": f["13"], "S2": f["15"], "H1": f["10"]}
+    from paper_1611_00606_amd.flops import paper_step_flops
+    f = paper_step_flops(np.full(512, 49), 9273, np.zeros(512, int))
+    want = {"loop1": f["loop1_zgemm_TBA_A"] + f["loop1_zhemm_TBB_B"], "S1": f["S_zherk_A"],
+            "S2": f["S_zherk_UB"], "H1": f["H_zher2k_Z_B"]}
     rows = [l.split() for l in open(os.path.join(GOLDEN, "tab6_nacl_kmax4.txt"))
             if l.strip() and not l.startswith("#")]
     assert len(rows) == 4
