@@ -84,16 +84,25 @@ enum {
  * the per-atom products are always binary64).
  *   HS_FP64       complex binary64 MFMA.
  *   HS_SPLIT_F16  split precision: each binary64 operand column is scaled by a
- *                 power of two and cut into 4 exact 9-bit integer slices held
- *                 in FP16; the slice products (pairs s + t <= 5) run on FP16
- *                 MFMA with FP32 accumulation (the two leading levels exact,
- *                 flushed every 32 contraction rows) and are recombined in
- *                 binary64. Error about 2^-35 of the operand column maxima per
- *                 product term (relative Frobenius error of H and S near 1e-10
- *                 for Gaussian operands, below 1e-9). Inputs must be finite. */
+ *                 power of two and cut into 4 exact integer slices of 8, 9,
+ *                 9, 9 bits held in FP16; the slice products (pairs
+ *                 s + t <= 5) run on FP16 MFMA with FP32 accumulation (the two
+ *                 leading levels exact, flushed every 64 contraction rows)
+ *                 and are recombined in binary64. Error about 2^-35 of the
+ *                 operand column maxima per product term (relative Frobenius
+ *                 error of H and S 2e-10 .. 4e-10 for Gaussian operands,
+ *                 below 1e-9). Inputs must be finite.
+ *   HS_SPLIT_I8   split precision on INT8 MFMA: the same column scaling, 5
+ *                 integer slices of 7 bits (int8; the first within +-127),
+ *                 the 15 pairs s + t <= 6 on INT8 MFMA with exact INT32
+ *                 accumulation per level, recombined in binary64 once per
+ *                 contraction segment. Error about 2^-35 of the operand
+ *                 column maxima per product term (same order as
+ *                 HS_SPLIT_F16). Inputs must be finite. */
 typedef enum {
     HS_FP64 = 0,
-    HS_SPLIT_F16 = 1
+    HS_SPLIT_F16 = 1,
+    HS_SPLIT_I8 = 2
 } hs_mode;
 
 /* Tile shapes of the batched per-atom stage (see hs_options.batch): shape id

@@ -14,6 +14,7 @@ from ._binding import (  # noqa: F401
     HS_ERR_UNSUPPORTED,
     HS_FP64,
     HS_SPLIT_F16,
+    HS_SPLIT_I8,
     HS_MAX_NL,
     HS_NUM_PHASE_EVENTS,
     HS_NUM_TILE_CONFIGS,

@@ -128,8 +128,8 @@ size_t AtomPlan::atom_bytes() const {
 
 size_t AtomPlan::kpoint_bytes(int n_g, int mode) const {
     size_t b = 2 * align_up(16 * (size_t)K * (size_t)n_g) + BatchBufs::bytes(n_atoms);
-    if (mode == HS_SPLIT_F16)
-        b += NSPLIT * (align_up(split_slice_bytes(K, n_g)) + align_up(8 * (size_t)n_g));
+    if (split_mode(mode))
+        b += NSPLIT * (align_up(slice_bytes(mode, K, n_g)) + align_up(8 * (size_t)n_g));
     return b;
 }
 
@@ -184,9 +184,9 @@ void KpointBufs::carve(const AtomPlan &p, int n_g, int mode, char *base) {
     for (int i = 0; i < NSPLIT; ++i) {
         sl[i] = nullptr;
         mx[i] = nullptr;
-        if (mode != HS_SPLIT_F16) continue;
+        if (!split_mode(mode)) continue;
         sl[i] = reinterpret_cast<_Float16 *>(base + o);
-        o += align_up(split_slice_bytes(p.K, n_g));
+        o += align_up(slice_bytes(mode, p.K, n_g));
         mx[i] = reinterpret_cast<unsigned long long *>(base + o);
         o += align_up(8 * (size_t)n_g);
     }
@@ -234,7 +234,7 @@ hipError_t enqueue_kpoint(const AtomPlan &p, const AtomBufs &ab, int n_g, int mo
     }
     if (e != hipSuccess) return e;
     if ((e = mark(2)) != hipSuccess) return e;
-    if (mode == HS_SPLIT_F16) {
+    if (split_mode(mode)) {
         // operands: 0 A, 1 U B, 2 Z, 3 B, 4 P3 (W, or A on failure-branch rows), 5 W
         const int K = p.K;
         const SliceSrc src[NSPLIT] = {
@@ -245,13 +245,17 @@ hipError_t enqueue_kpoint(const AtomPlan &p, const AtomBufs &ab, int n_g, int mo
             {kb.W, A, ab.sel + 2 * (size_t)K, nullptr, kb.mx[4], kb.sl[4]},
             {kb.W, nullptr, nullptr, nullptr, kb.mx[5], kb.sl[5]},
         };
-        for (int i = 0; i < NSPLIT; ++i)
-            if ((e = launch_slice(src[i], K, n_g, st)) != hipSuccess) return e;
+        for (int i = 0; i < NSPLIT; ++i) {
+            e = mode == HS_SPLIT_I8 ? launch_slice8(src[i], K, n_g, st)
+                                    : launch_slice(src[i], K, n_g, st);
+            if (e != hipSuccess) return e;
+        }
         SliceView v[NSPLIT];
         for (int i = 0; i < NSPLIT; ++i) v[i] = SliceView{kb.sl[i], kb.mx[i]};
         const SliceView hseg[3][2] = {{v[2], v[3]}, {v[3], v[2]}, {v[4], v[5]}};
         const SliceView sseg[2][2] = {{v[0], v[0]}, {v[1], v[1]}};
-        e = launch_split_reduce(K, n_g, hseg, sseg, H, S, st);
+        e = mode == HS_SPLIT_I8 ? launch_split8_reduce(K, n_g, hseg, sseg, H, S, st)
+                                : launch_split_reduce(K, n_g, hseg, sseg, H, S, st);
     } else {
         e = launch_reduce(p.K, n_g, A, B, kb.Z, kb.W, ab.sel, ab.d, H, S, st);
     }

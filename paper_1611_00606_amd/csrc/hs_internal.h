@@ -55,7 +55,10 @@ void set_error(const std::string &msg);
 const std::string &last_error();
 int hip_fail(hipError_t e, const char *where);   // records the message, returns HS_ERR_HIP
 int check_device();                              // HS_OK on gfx950, else an error status
-inline bool valid_mode(int mode) { return mode == 0 || mode == 1; }   // HS_FP64, HS_SPLIT_F16
+inline bool valid_mode(int mode) {   // HS_FP64, HS_SPLIT_F16, HS_SPLIT_I8
+    return mode == HS_FP64 || mode == HS_SPLIT_F16 || mode == HS_SPLIT_I8;
+}
+inline bool split_mode(int mode) { return mode == HS_SPLIT_F16 || mode == HS_SPLIT_I8; }
 
 // Split-precision reductions (k_split.hip). A sliced operand: rows of X (or
 // of Xalt where sel[k] != 0), optionally scaled by sqrt(rscale[k]); outputs
@@ -79,6 +82,16 @@ hipError_t launch_slice(const SliceSrc &src, int K, int n_g, hipStream_t st);
 hipError_t launch_split_reduce(int K, int n_g, const SliceView (&hseg)[3][2],
                                const SliceView (&sseg)[2][2], double2 *H, double2 *S,
                                hipStream_t st);
+// INT8 form: slices S8 [5][groups][N_G][16 int8], groups = 4 * ceil(K / 32);
+// same column maxima and segments as the FP16 form.
+size_t split8_slice_bytes(int K, int n_g);
+hipError_t launch_slice8(const SliceSrc &src, int K, int n_g, hipStream_t st);
+hipError_t launch_split8_reduce(int K, int n_g, const SliceView (&hseg)[3][2],
+                                const SliceView (&sseg)[2][2], double2 *H, double2 *S,
+                                hipStream_t st);
+inline size_t slice_bytes(int mode, int K, int n_g) {
+    return mode == HS_SPLIT_I8 ? split8_slice_bytes(K, n_g) : split_slice_bytes(K, n_g);
+}
 // upper := conj(lower), Im(diag) := 0 for both outputs
 hipError_t launch_mirror(double2 *H, double2 *S, int n_g, hipStream_t st);
 

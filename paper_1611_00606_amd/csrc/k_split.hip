@@ -206,7 +206,7 @@ struct SplitArgs {
     int nt, ntri, ntri8;
 };
 
-__device__ __forceinline__ void sband_tile(int t, int nt, int &ti, int &tj) {
+__device__ __forceinline__ void sband_tile(int t, int nt, int &ti, int &tj, int band = SBAND) {
     int c0 = 0;
     for (;;) {
         const int m = nt - c0;
@@ -214,7 +214,7 @@ __device__ __forceinline__ void sband_tile(int t, int nt, int &ti, int &tj) {
             ti = tj = -1;
             return;
         }
-        const int w = m < SBAND ? m : SBAND;
+        const int w = m < band ? m : band;
         const int tri = w * (w + 1) / 2;
         const int cnt = tri + (m - w) * w;
         if (t < cnt) {
@@ -231,7 +231,7 @@ __device__ __forceinline__ void sband_tile(int t, int nt, int &ti, int &tj) {
             return;
         }
         t -= cnt;
-        c0 += SBAND;
+        c0 += band;
     }
 }
 
@@ -451,6 +451,282 @@ k_split_reduce(SplitArgs args) {
     }
 }
 
+
+// ===========================================================================
+// INT8 form (HS_SPLIT_I8). Same scaling and complex interleaving, integer
+// slices of 7 bits on V_MFMA_I32_16X16X64_I8 with exact INT32 accumulation.
+//
+// Slicing: with e[n] such that max |X[.][n]| * 128/127 < 2^e[n], x = X 2^-e
+// lies in (-127/128, 127/128) and
+//     x = sum_{s=1..5} sig_s 128^-s + r,   sig_1 = rint(128 x) in [-127, 127],
+//     sig_s = rint(128 r_{s-1}) in [-64, 64] (s >= 2),  |r| <= 2^-36,
+// every value an int8. A pair (s, t) weighs 128^-(s + t); the 15 pairs with
+// s + t <= 6 go into five INT32 level accumulators (c = 2..6). A level sums
+// at most 5 pairs of |sig sig'| <= 127 * 64 or 64 * 64 (level 2: 127^2), at
+// most 28544 < 2^15 per real product, so a level stays exact for 2^16 real
+// products: the accumulators are combined in FP64 (Horner, scaled by
+// 2^(eP + eQ - 14)) only at the end of each (P, Q) segment and every 32768
+// complex rows, and added to the output tile in memory (written by the first
+// flush, read-modified-written by later ones, by the same thread in a fixed
+// order: deterministic). No FP64 accumulator is held during the K loop.
+//
+// Errors left: remainders (2^-36 of the column maxima on each side),
+// dropped pairs (s + t = 7: four pairs of |sig sig'| <= 2^12 at 2^-49, i.e.
+// 2^-35), FP64 rounding.
+//
+// Tiles: 64 x 64, HS_SPLIT8_WAVES waves (8: 2 x 4 waves of 32 x 16; 4: 2 x 2
+// waves of 32 x 32). A stage is 32 complex rows (one MFMA K step of 64
+// int8). Operand slices go straight from global memory to LDS (16-byte
+// direct loads of 64 columns; 40 per stage), double-buffered in two 40 KiB
+// LDS arrays, so no staging registers are needed.
+
+#ifndef HS_SPLIT8_WAVES
+#define HS_SPLIT8_WAVES 8
+#endif
+
+typedef int i4 __attribute__((ext_vector_type(4)));
+typedef unsigned short us2 __attribute__((ext_vector_type(2)));
+
+constexpr int NSL8 = 5;                  // slices per value
+constexpr int NLEV8 = 5;                 // levels c = 2 .. 6
+constexpr int B8 = 64;                   // tile rows (g') = tile cols (g)
+constexpr int NW8 = HS_SPLIT8_WAVES;
+constexpr int W8M = 2, W8N = NW8 / 2;    // waves
+constexpr int NT8 = 64 * NW8;
+constexpr int T8M = B8 / W8M / 16, T8N = B8 / W8N / 16;   // 16x16 blocks per wave
+constexpr int GRP8 = 4;                  // groups of 8 complex rows per stage = 32 rows
+constexpr int OP8_ITEMS = NSL8 * GRP8 * B8;   // 16-byte items per operand per stage
+constexpr int BUF8 = 2 * OP8_ITEMS;
+constexpr int FLUSH8 = 1024;                  // stages (32768 complex rows) per flush
+constexpr int BAND8 = 8;
+static_assert(NW8 == 4 || NW8 == 8, "4 or 8 waves");
+static_assert(T8M >= 1 && T8N >= 1, "wave tiling");
+static_assert((long long)FLUSH8 * 64 * 28544 < (1LL << 31), "levels exact in INT32");
+
+// exponent e with column max * 128/127 < 2^e (0 for an all-zero column)
+__device__ __forceinline__ int col_exp8(const unsigned long long *mx, int n) {
+    const double m = __longlong_as_double((long long)mx[n]);
+    int e = 0;
+    if (m > 0.0) frexp(m * (128.0 / 127.0), &e);
+    return e;
+}
+
+// One thread per (group of 8 complex rows, column): 16 interleaved real
+// values -> 5 slices of 16 int8, written to S8[s][g][n][0..15].
+__global__ void __launch_bounds__(256)
+k_slice8(SliceSrc src, int K, int n_g, int groups) {
+    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+    const int n = (int)(idx % n_g);
+    const int g = (int)(idx / n_g);
+    if (g >= groups) return;
+    const double sc = ldexp(1.0, -col_exp8(src.mx, n));
+    double x[16];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int k = 8 * g + q;
+        double2 v = {0.0, 0.0};
+        if (k < K) v = slice_src_row(src, k, n_g, n);
+        x[2 * q] = v.x * sc;
+        x[2 * q + 1] = v.y * sc;
+    }
+    const long long plane = (long long)groups * n_g;   // 16-byte items per slice
+    uint4 *out = reinterpret_cast<uint4 *>(src.S) + (long long)g * n_g + n;
+#pragma unroll
+    for (int s = 0; s < NSL8; ++s) {
+        unsigned w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const double t = x[j] * 128.0;
+            double sig = rint(t);
+            sig = fmin(fmax(sig, -127.0), 127.0);
+            x[j] = t - sig;
+            w[j >> 2] |= ((unsigned)(int)sig & 0xffu) << (8 * (j & 3));
+        }
+        out[s * plane] = uint4{w[0], w[1], w[2], w[3]};
+    }
+}
+
+struct Split8Seg {
+    const uint4 *P, *Q;                     // slices [5][groups][n_g] x 16 B
+    const unsigned long long *mP, *mQ;      // column maxima [n_g]
+};
+
+struct Split8Args {
+    Split8Seg h[3];
+    Split8Seg s[2];
+    double2 *H, *S;
+    int n_g, groups;          // groups of 8 complex rows, a multiple of GRP8
+    int nt, ntri, ntri8;
+};
+
+// (Re, Im) byte pairs -> (Im, -Re): conj(p) q's imaginary part as a dot product.
+__device__ __forceinline__ unsigned im_pairs(unsigned d) {
+    const unsigned t = __builtin_amdgcn_perm(d, d, 0x02030001u) ^ 0xff00ff00u;
+    us2 h = __builtin_bit_cast(us2, t);
+    h += us2{0x0100, 0x0100};   // per 16-bit half: high byte ~b + 1 = -b, no carry across
+    return __builtin_bit_cast(unsigned, h);
+}
+
+__device__ __forceinline__ void split8_segment(const Split8Seg sg, int n_g, int groups, int m0,
+                                               int n0, bool first, double2 *out, uint4 *bufA,
+                                               uint4 *bufB) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave % W8M, wn = wave / W8M;
+    const long long plane = (long long)groups * n_g;
+    const int nstage = groups / GRP8;
+
+    // direct loads of stage st into buf (40 of 64 columns each): with 8 waves
+    // wave w loads group w % 4 of every slice of operand w / 4; with 4 waves
+    // group w of both operands
+    constexpr int OPS_PER_WAVE = NW8 == 8 ? 1 : 2;
+    const int grp_w = wave % GRP8;
+    const int op0 = NW8 == 8 ? wave / GRP8 : 0;
+    int pc = m0 + lane;
+    pc = pc < n_g ? pc : n_g - 1;
+    int qc = n0 + lane;
+    qc = qc < n_g ? qc : n_g - 1;
+    auto issue = [&](uint4 *buf, int st) __attribute__((always_inline)) {
+        const long long so = (long long)(st * GRP8 + grp_w) * n_g;
+#pragma unroll
+        for (int o = 0; o < OPS_PER_WAVE; ++o) {
+            const int op = op0 + o;
+            const uint4 *base = (op == 0 ? sg.P + pc : sg.Q + qc) + so;
+            uint4 *dst = buf + op * OP8_ITEMS + grp_w * B8;
+#pragma unroll
+            for (int s = 0; s < NSL8; ++s)
+                __builtin_amdgcn_global_load_lds(base + s * plane, dst + s * GRP8 * B8, 16, 0, 0);
+        }
+    };
+
+    i4 lre[T8M][T8N][NLEV8], lim[T8M][T8N][NLEV8];
+    auto clear = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int i = 0; i < T8M; ++i)
+#pragma unroll
+            for (int j = 0; j < T8N; ++j)
+#pragma unroll
+                for (int c = 0; c < NLEV8; ++c) {
+                    lre[i][j][c] = i4{0, 0, 0, 0};
+                    lim[i][j][c] = i4{0, 0, 0, 0};
+                }
+    };
+    const int lg = lane >> 4, lc = lane & 15;
+    auto compute = [&](const uint4 *buf) __attribute__((always_inline)) {
+        const uint4 *lp = buf;
+        const uint4 *lq = buf + OP8_ITEMS;
+        i4 a[T8M][NSL8];
+#pragma unroll
+        for (int s = 0; s < NSL8; ++s)
+#pragma unroll
+            for (int i = 0; i < T8M; ++i)
+                a[i][s] = __builtin_bit_cast(i4, lp[(s * GRP8 + lg) * B8 + wm * (B8 / W8M) + i * 16 + lc]);
+#pragma unroll
+        for (int t = 0; t < NSL8; ++t)
+#pragma unroll
+            for (int j = 0; j < T8N; ++j) {
+                const uint4 u = lq[(t * GRP8 + lg) * B8 + wn * (B8 / W8N) + j * 16 + lc];
+                const i4 b = __builtin_bit_cast(i4, u);
+                const i4 bi = i4{(int)im_pairs(u.x), (int)im_pairs(u.y), (int)im_pairs(u.z),
+                                 (int)im_pairs(u.w)};
+#pragma unroll
+                for (int s = 0; s + t < NLEV8; ++s) {   // levels (s+1)+(t+1) <= 6
+                    const int c = s + t;
+#pragma unroll
+                    for (int i = 0; i < T8M; ++i) {
+                        lre[i][j][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i][s], b, lre[i][j][c], 0, 0, 0);
+                        lim[i][j][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i][s], bi, lim[i][j][c], 0, 0, 0);
+                    }
+                }
+            }
+    };
+    // levels -> FP64, scaled, into the output tile (lower triangle only)
+    auto flush = [&](bool write) __attribute__((always_inline)) {
+#pragma unroll
+        for (int j = 0; j < T8N; ++j) {
+            const int g = n0 + wn * (B8 / W8N) + j * 16 + lc;
+            const int eq = col_exp8(sg.mQ, g < n_g ? g : n_g - 1);
+#pragma unroll
+            for (int i = 0; i < T8M; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int gp = m0 + wm * (B8 / W8M) + i * 16 + 4 * lg + v;
+                    if (gp < n_g && g <= gp) {
+                        const double w = ldexp(1.0, col_exp8(sg.mP, gp) + eq - 14);
+                        double tr = (double)lre[i][j][NLEV8 - 1][v];
+                        double ti = (double)lim[i][j][NLEV8 - 1][v];
+#pragma unroll
+                        for (int c = NLEV8 - 2; c >= 0; --c) {
+                            tr = fma(tr, 1.0 / 128.0, (double)lre[i][j][c][v]);
+                            ti = fma(ti, 1.0 / 128.0, (double)lim[i][j][c][v]);
+                        }
+                        double2 *o = out + (long long)gp * n_g + g;
+                        double2 r = double2{tr * w, ti * w};
+                        if (!write) {
+                            const double2 prev = *o;
+                            r.x += prev.x;
+                            r.y += prev.y;
+                        }
+                        *o = r;
+                    }
+                }
+        }
+        clear();
+    };
+
+    clear();
+    issue(bufA, 0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    bool fresh = first;
+    // chunks of FLUSH8 stages; stage st is in bufA (st even) or bufB, and the
+    // next stage is loaded into the other buffer while st is computed
+    for (int c0 = 0; c0 < nstage; c0 += FLUSH8) {
+        const int c1 = nstage < c0 + FLUSH8 ? nstage : c0 + FLUSH8;
+        for (int st = c0; st < c1; ++st) {
+            uint4 *cur = (st & 1) ? bufB : bufA;
+            uint4 *nxt = (st & 1) ? bufA : bufB;
+            if (st + 1 < nstage) issue(nxt, st + 1);
+            compute(cur);
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+        }
+        flush(fresh);
+        fresh = false;
+    }
+}
+
+__global__ void __launch_bounds__(NT8)
+k_split8_reduce(Split8Args args) {
+    __shared__ uint4 bufA[BUF8];
+    __shared__ uint4 bufB[BUF8];
+
+    int b = blockIdx.x;
+    const bool isH = b < args.ntri8;
+    if (!isH) b -= args.ntri8;
+    const int per_xcd = args.ntri8 / 8;
+    const int t = (b % 8) * per_xcd + b / 8;
+    if (t >= args.ntri) return;
+    int ti, tj;
+    sband_tile(t, args.nt, ti, tj, BAND8);
+    if (ti < 0) return;
+    const int m0 = ti * B8, n0 = tj * B8;
+    const int n_g = args.n_g;
+
+    double2 *out = isH ? args.H : args.S;
+    if (isH) {
+        const Split8Seg h0 = args.h[0], h1 = args.h[1], h2 = args.h[2];
+        split8_segment(h0, n_g, args.groups, m0, n0, true, out, bufA, bufB);
+        split8_segment(h1, n_g, args.groups, m0, n0, false, out, bufA, bufB);
+        split8_segment(h2, n_g, args.groups, m0, n0, false, out, bufA, bufB);
+    } else {
+        const Split8Seg s0 = args.s[0], s1 = args.s[1];
+        split8_segment(s0, n_g, args.groups, m0, n0, true, out, bufA, bufB);
+        split8_segment(s1, n_g, args.groups, m0, n0, false, out, bufA, bufB);
+    }
+}
+
 }  // namespace
 
 size_t split_slice_bytes(int K, int n_g) {
@@ -488,6 +764,45 @@ hipError_t launch_split_reduce(int K, int n_g, const SliceView (&hseg)[3][2],
     a.ntri = a.nt * (a.nt + 1) / 2;
     a.ntri8 = (a.ntri + 7) / 8 * 8;
     hipLaunchKernelGGL(k_split_reduce, dim3(2 * a.ntri8), dim3(SNT), 0, st, a);
+    return hipGetLastError();
+}
+
+size_t split8_slice_bytes(int K, int n_g) {
+    const long long groups = (long long)((K + 31) / 32) * GRP8;
+    return (size_t)NSL8 * groups * n_g * 16;
+}
+
+hipError_t launch_slice8(const SliceSrc &src, int K, int n_g, hipStream_t st) {
+    const int groups = (K + 31) / 32 * GRP8;
+    hipLaunchKernelGGL(k_zero_u64, dim3((n_g + 255) / 256), dim3(256), 0, st, src.mx, n_g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_colmax, dim3((n_g + 63) / 64, (K + CROWS - 1) / CROWS), dim3(256), 0, st,
+                       src, K, n_g);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const long long items = (long long)groups * n_g;
+    hipLaunchKernelGGL(k_slice8, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, st, src, K,
+                       n_g, groups);
+    return hipGetLastError();
+}
+
+hipError_t launch_split8_reduce(int K, int n_g, const SliceView (&hseg)[3][2],
+                                const SliceView (&sseg)[2][2], double2 *H, double2 *S,
+                                hipStream_t st) {
+    auto u4 = [](const _Float16 *p) { return reinterpret_cast<const uint4 *>(p); };
+    Split8Args a;
+    for (int i = 0; i < 3; ++i)
+        a.h[i] = Split8Seg{u4(hseg[i][0].S), u4(hseg[i][1].S), hseg[i][0].mx, hseg[i][1].mx};
+    for (int i = 0; i < 2; ++i)
+        a.s[i] = Split8Seg{u4(sseg[i][0].S), u4(sseg[i][1].S), sseg[i][0].mx, sseg[i][1].mx};
+    a.H = H;
+    a.S = S;
+    a.n_g = n_g;
+    a.groups = (K + 31) / 32 * GRP8;
+    a.nt = (n_g + B8 - 1) / B8;
+    a.ntri = a.nt * (a.nt + 1) / 2;
+    a.ntri8 = (a.ntri + 7) / 8 * 8;
+    hipLaunchKernelGGL(k_split8_reduce, dim3(2 * a.ntri8), dim3(NT8), 0, st, a);
     return hipGetLastError();
 }
 

@@ -90,7 +90,7 @@ def test_build_ex_option_checks():
     lib = P.load_library()
     assert lib.hs_build_ex(*[FAKE] * 6, 2, 4, 8, FAKE, FAKE, None) == -12
     opt = Bd.hs_options()
-    opt.mode = 5
+    opt.mode = 3
     assert lib.hs_build_ex(*[FAKE] * 6, 2, 4, 8, FAKE, FAKE, ctypes.byref(opt)) == -12
     nl = np.array([4, 200], np.int32)
     opt = Bd.hs_options()
@@ -147,7 +147,11 @@ def test_split_mode_workspace():
     K = 490
     groups = (K + 15) // 16 * 4
     assert split >= fp64 + 6 * 4 * groups * 1000 * 16
-    assert P.hs_workspace_bytes(10, None, 49, 1000, 2) == 0
+    i8 = P.hs_workspace_bytes(10, None, 49, 1000, P.HS_SPLIT_I8)
+    groups8 = (K + 31) // 32 * 4
+    assert i8 >= fp64 + 6 * 5 * groups8 * 1000 * 16
+    assert i8 < split   # 5 bytes per real value against 8
+    assert P.hs_workspace_bytes(10, None, 49, 1000, 3) == 0
 
 
 def test_tile_configs():

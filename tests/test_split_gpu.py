@@ -1,4 +1,4 @@
-"""Split-precision form (HS_SPLIT_F16) against the CPU oracle.
+"""Split-precision forms (HS_SPLIT_F16, HS_SPLIT_I8) against the CPU oracle.
 
 The tolerance is the spec one for this form: relative Frobenius error
 <= 1e-9 for H and for S, each stated separately. The outputs stay exactly
@@ -16,6 +16,7 @@ pytestmark = pytest.mark.gpu
 
 TOL = 1e-9
 SPLIT = 1
+MODES = [1, 2]   # HS_SPLIT_F16, HS_SPLIT_I8
 
 
 def _run(p, mode=SPLIT):
@@ -82,16 +83,18 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("name", list(CASES))
-def test_split_parity(name):
+def test_split_parity(name, mode):
     p = CASES[name]()
-    _check(p, _run(p))
+    _check(p, _run(p, mode))
 
 
-def test_split_deterministic():
+@pytest.mark.parametrize("mode", MODES)
+def test_split_deterministic(mode):
     import torch
     p = make_problem(4, 33, 700, seed=8, fail_atoms=[2])
-    r = _run(p)
+    r = _run(p, mode)
     H1, S1, _ = r.results()
     r.H.zero_()
     r.S.zero_()
@@ -101,11 +104,12 @@ def test_split_deterministic():
     assert np.array_equal(H1, H2) and np.array_equal(S1, S2)
 
 
-def test_split_full_size_sampled():
+@pytest.mark.parametrize("mode", MODES)
+def test_split_full_size_sampled(mode):
     """N_G = 8000, N_A = 100, N_L = 81 on sampled columns and bilinear probes."""
     import torch
     p = make_config("precision", seed=0)
-    r = _run(p)
+    r = _run(p, mode)
     rng = np.random.default_rng(1)
     cols = sorted(set([0, 63, 64, 4000, p.N_G - 1] + rng.integers(0, p.N_G, 6).tolist()))
     idx = torch.as_tensor(np.asarray(cols), device=r.H.device)
@@ -126,12 +130,13 @@ def test_split_full_size_sampled():
         assert abs(y.conj() @ (Sd @ x) - s) <= TOL * np.linalg.norm(Sd) * nx * ny
 
 
-def test_split_in_serving_context():
+@pytest.mark.parametrize("mode", MODES)
+def test_split_in_serving_context(mode):
     """The resident context builds in split mode too (same result as one-shot)."""
     import torch
     from paper_1611_00606_amd.serving import Context
     p = make_problem(3, 25, 450, seed=9, fail_atoms=[0])
-    r = _run(p)
+    r = _run(p, mode)
     H1, S1, _ = r.results()
     ctx = Context(p.T_AA, p.T_AB, p.T_BB, p.U, p.nl)
     dev = torch.device("cuda:0")
@@ -139,8 +144,8 @@ def test_split_in_serving_context():
     Bm = torch.from_numpy(p.B).to(dev)
     H = torch.empty((p.N_G, p.N_G), dtype=torch.complex128, device=dev)
     S = torch.empty_like(H)
-    ws = torch.empty(ctx.workspace_bytes(p.N_G, SPLIT), dtype=torch.uint8, device=dev)
-    ctx.build(A, Bm, p.N_G, H, S, ws, mode=SPLIT)
+    ws = torch.empty(ctx.workspace_bytes(p.N_G, mode), dtype=torch.uint8, device=dev)
+    ctx.build(A, Bm, p.N_G, H, S, ws, mode=mode)
     torch.cuda.synchronize()
     assert np.array_equal(H.cpu().numpy(), H1) and np.array_equal(S.cpu().numpy(), S1)
     ctx.close()
