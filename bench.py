@@ -35,6 +35,10 @@ HBM_PEAK_GBS = 8000.0
 # complex multiply-add (8 FP64 flops) 10 slice pairs x 2 MFMAs (Re, Im) x 2
 # interleaved real products x 2 flops = 80.
 SPLIT_F16_PER_FP64 = 10.0
+INT8_MFMA_PEAK_TOPS = 5000.0    # MI355X dense INT8 matrix peak
+# INT8 MFMA ops per FP64 flop: 15 slice pairs x 2 MFMAs x 2 interleaved
+# products x 2 ops = 120 per complex multiply-add (8 FP64 flops).
+SPLIT_I8_PER_FP64 = 15.0
 
 
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_reduce_precision_ng8000.md")
@@ -45,7 +49,6 @@ def measured_traffic(config: str):
     """HBM bytes per k_reduce launch from the committed rocprofv3 counter
     record, or None when the record is for another workload or the kernel's
     sources have changed since the counters were taken."""
-    import hashlib
     if config != "precision" or not os.path.exists(TRAFFIC_RECORD):
         return None
     rec = {}
@@ -53,12 +56,23 @@ def measured_traffic(config: str):
         if ":" in line and line.split(":")[0] in ("source_sha256", "traffic_bytes"):
             k, v = line.split(":", 1)
             rec[k.strip()] = v.strip()
-    h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
-        h.update(open(os.path.join(ROOT, f), "rb").read())
-    if rec.get("source_sha256") != h.hexdigest() or "traffic_bytes" not in rec:
+    if rec.get("source_sha256") != kernel_source_digest() or "traffic_bytes" not in rec:
         return None
     return float(rec["traffic_bytes"])
+
+
+def kernel_source_digest() -> str:
+    """SHA-256 of k_reduce's sources with comments and whitespace removed, so
+    that a change of the code (not of its comments) invalidates the record."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        text = open(os.path.join(ROOT, f)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        h.update(re.sub(r"\s+", "", text).encode())
+    return h.hexdigest()
 
 
 class HipEvents:
@@ -145,16 +159,31 @@ def timed_builds(run, steps: int, warmup: int, hip):
     return ph, total
 
 
-def split_bench(p, steps: int, warmup: int, fp64_ms: float, hip, n_cols: int = 12):
+SPLIT_MODES = {
+    1: dict(name="split_f16",
+            mode="split_f16 (slices of 8+9+9+9 bits in FP16, 10 slice pairs on FP16 MFMA, FP32 "
+                 "accumulation flushed every 64 rows, FP64 recombination)",
+            per_fp64=SPLIT_F16_PER_FP64, peak=FP16_MFMA_PEAK_TFLOPS,
+            unit="TFLOP/s (FP16 MFMA flops issued)"),
+    2: dict(name="split_i8",
+            mode="split_i8 (five 7-bit int8 slices, 15 slice pairs on INT8 MFMA, exact INT32 "
+                 "accumulation per level, FP64 recombination per segment)",
+            per_fp64=SPLIT_I8_PER_FP64, peak=INT8_MFMA_PEAK_TOPS,
+            unit="TOP/s (INT8 MFMA ops issued)"),
+}
+
+
+def split_bench(p, steps: int, warmup: int, fp64_ms: float, hip, mode: int, n_cols: int = 12):
     """Split-precision form on the same workload: time, speedup over the FP64
     path, and relative Frobenius error of H and of S against the CPU oracle
     on sampled columns."""
     import torch
     import oracle
-    from paper_1611_00606_amd import HS_SPLIT_F16, DeviceBuild
+    from paper_1611_00606_amd import DeviceBuild
     from paper_1611_00606_amd.flops import algorithmic_flops, reduction_flops
 
-    run = DeviceBuild.from_problem(p, device="cuda:0", mode=HS_SPLIT_F16)
+    m = SPLIT_MODES[mode]
+    run = DeviceBuild.from_problem(p, device="cuda:0", mode=mode)
     ph, total = timed_builds(run, steps, warmup, hip)
     info = run.info.cpu().numpy()
     rng = np.random.default_rng(1234)
@@ -167,9 +196,9 @@ def split_bench(p, steps: int, warmup: int, fp64_ms: float, hip, n_cols: int = 1
     Hr = oracle.hamiltonian_columns(p.A, p.B, p.T_AA, p.T_AB, p.T_BB, p.nl, cols)
     Sr = oracle.overlap_columns(p.A, p.B, p.U, p.nl, cols)
     f = algorithmic_flops(p.nl, p.N_G, info)
+    issued = m["per_fp64"] * reduction_flops(p.nl, p.N_G) / (ph[2] * 1e-3) / 1e12
     return {
-        "mode": "split_f16 (slices of 8+9+9+9 bits in FP16, 10 slice pairs on FP16 MFMA, FP32 "
-                "accumulation flushed every 64 rows, FP64 recombination)",
+        "mode": m["mode"],
         "ms_per_step": round(total, 3),
         "value": round(f / (total * 1e-3) / 1e12, 3),
         "unit": "TFLOP/s (FP64-equivalent)",
@@ -177,13 +206,12 @@ def split_bench(p, steps: int, warmup: int, fp64_ms: float, hip, n_cols: int = 1
         "phases_ms": {"prep_cholesky": round(float(ph[0]), 4), "atom_products": round(float(ph[1]), 4),
                       "slice_and_reduce_HS": round(float(ph[2]), 4), "mirror": round(float(ph[3]), 4)},
         "roofline": {
-            "kernel": "k_slice + k_split_reduce (phase 2..3)",
+            "kernel": "slicing + split reduction (phase 2..3)",
             "bound": "mfma",
-            "achieved": round(SPLIT_F16_PER_FP64 * reduction_flops(p.nl, p.N_G) / (ph[2] * 1e-3) / 1e12, 2),
-            "peak": FP16_MFMA_PEAK_TFLOPS,
-            "unit": "TFLOP/s (FP16 MFMA flops issued)",
-            "frac": round(SPLIT_F16_PER_FP64 * reduction_flops(p.nl, p.N_G) / (ph[2] * 1e-3) / 1e12
-                          / FP16_MFMA_PEAK_TFLOPS, 4),
+            "achieved": round(issued, 2),
+            "peak": m["peak"],
+            "unit": m["unit"],
+            "frac": round(issued / m["peak"], 4),
         },
         "rel_err_H": float(np.linalg.norm(Hc - Hr) / np.linalg.norm(Hr)),
         "rel_err_S": float(np.linalg.norm(Sc - Sr) / np.linalg.norm(Sr)),
@@ -296,7 +324,7 @@ def serving_bench(seed: int, n_slots: int = 4, arena_gb: float = 24.0, n_sets: i
     out["latency_samples"] = len(reqs) * streams
     out["offered_rate_per_s"] = [round(x, 3) for x in offered]
     out.update({
-        "mode": "split_f16" if mode else "fp64",
+        "mode": {0: "fp64", 1: "split_f16", 2: "split_i8"}[mode],
         "workload": "64 requests, N_A=64 atoms, N_L=64, N_G uniform in [1500, 9000], Poisson arrivals",
         "arrival_rate_per_s": rate,   # nominal Poisson rate; offered_rate_per_s is realized
         "load": load,
@@ -432,7 +460,9 @@ def main():
     if not args.no_split:
         print("bench: split precision", file=sys.stderr, flush=True)
         hip = HipEvents()
-        out["split"] = split_bench(p, max(3, args.steps // 2), 1, ms_step, hip)
+        for mode in (1, 2):
+            out[SPLIT_MODES[mode]["name"]] = split_bench(p, max(3, args.steps // 2), 1, ms_step,
+                                                         hip, mode)
     if not args.no_batching:
         print("bench: batched per-atom stage", file=sys.stderr, flush=True)
         out["batching"] = batching_bench(args.seed, max(3, args.steps // 2), HipEvents())
@@ -442,7 +472,7 @@ def main():
         print("bench: serving stream", file=sys.stderr, flush=True)
         out["serving"] = serving_bench(args.seed)
         if not args.no_split:
-            out["serving_split"] = serving_bench(args.seed, mode=1)
+            out["serving_split_i8"] = serving_bench(args.seed, mode=2)
     print(json.dumps(out), flush=True)
 
 
