@@ -350,6 +350,8 @@ def main():
                     help="skip the serving-form measurement (k-point builds/s, p50/p99)")
     ap.add_argument("--no-split", action="store_true",
                     help="skip the split-precision measurement")
+    ap.add_argument("--split-modes", default="1,2",
+                    help="split modes to measure (1 = HS_SPLIT_F16, 2 = HS_SPLIT_I8)")
     ap.add_argument("--no-batching", action="store_true",
                     help="skip the batched per-atom stage measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -460,7 +462,7 @@ def main():
     if not args.no_split:
         print("bench: split precision", file=sys.stderr, flush=True)
         hip = HipEvents()
-        for mode in (1, 2):
+        for mode in [int(m) for m in args.split_modes.split(",") if m]:
             out[SPLIT_MODES[mode]["name"]] = split_bench(p, max(3, args.steps // 2), 1, ms_step,
                                                          hip, mode)
     if not args.no_batching:

@@ -477,11 +477,18 @@ k_split_reduce(SplitArgs args) {
 // Tiles: 64 x 64, HS_SPLIT8_WAVES waves (8: 2 x 4 waves of 32 x 16; 4: 2 x 2
 // waves of 32 x 32). A stage is 32 complex rows (one MFMA K step of 64
 // int8). Operand slices go straight from global memory to LDS (16-byte
-// direct loads of 64 columns; 40 per stage), double-buffered in two 40 KiB
-// LDS arrays, so no staging registers are needed.
+// direct loads of 64 columns; 40 per stage) through a ring of 40 KiB LDS
+// buffers, so no staging registers are needed.
 
 #ifndef HS_SPLIT8_WAVES
 #define HS_SPLIT8_WAVES 8
+#endif
+// LDS buffers in the load ring (2: next stage in flight; 3: two stages)
+#ifndef HS_SPLIT8_RING
+#define HS_SPLIT8_RING 2
+#endif
+#ifndef HS_SPLIT8_BAND
+#define HS_SPLIT8_BAND 8
 #endif
 
 typedef int i4 __attribute__((ext_vector_type(4)));
@@ -498,8 +505,10 @@ constexpr int GRP8 = 4;                  // groups of 8 complex rows per stage =
 constexpr int OP8_ITEMS = NSL8 * GRP8 * B8;   // 16-byte items per operand per stage
 constexpr int BUF8 = 2 * OP8_ITEMS;
 constexpr int FLUSH8 = 1024;                  // stages (32768 complex rows) per flush
-constexpr int BAND8 = 8;
+constexpr int BAND8 = HS_SPLIT8_BAND;
+constexpr int RING8 = HS_SPLIT8_RING;
 static_assert(NW8 == 4 || NW8 == 8, "4 or 8 waves");
+static_assert(RING8 == 2 || RING8 == 3, "2 or 3 LDS buffers");
 static_assert(T8M >= 1 && T8N >= 1, "wave tiling");
 static_assert((long long)FLUSH8 * 64 * 28544 < (1LL << 31), "levels exact in INT32");
 
@@ -568,8 +577,8 @@ __device__ __forceinline__ unsigned im_pairs(unsigned d) {
 }
 
 __device__ __forceinline__ void split8_segment(const Split8Seg sg, int n_g, int groups, int m0,
-                                               int n0, bool first, double2 *out, uint4 *bufA,
-                                               uint4 *bufB) {
+                                               int n0, bool first, double2 *out, uint4 *bufs0,
+                                               uint4 *bufs1, uint4 *bufs2) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -676,20 +685,36 @@ __device__ __forceinline__ void split8_segment(const Split8Seg sg, int n_g, int 
     };
 
     clear();
-    issue(bufA, 0);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    // Ring of RING8 LDS buffers: stage st lives in buf[st % RING8]; the
+    // loads of the next RING8 - 1 stages are in flight while st is computed.
+    // Each wave issues LOADS_PER_WAVE direct loads per stage, so waiting
+    // until at most (RING8 - 2) * LOADS_PER_WAVE of them are outstanding
+    // completes the oldest stage in flight.
+    constexpr int LOADS_PER_WAVE = NSL8 * OPS_PER_WAVE;
+    auto bufp = [&](int st) __attribute__((always_inline)) {
+        const int r = st % RING8;
+        return r == 0 ? bufs0 : r == 1 ? bufs1 : bufs2;
+    };
+    auto wait_oldest = [&](bool more_in_flight) __attribute__((always_inline)) {
+        if (RING8 == 3 && more_in_flight) {
+            static_assert(LOADS_PER_WAVE == 5 || LOADS_PER_WAVE == 10, "waitcnt immediates");
+            if constexpr (LOADS_PER_WAVE == 5) asm volatile("s_waitcnt vmcnt(5)" ::: "memory");
+            else asm volatile("s_waitcnt vmcnt(10)" ::: "memory");
+        } else {
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        }
+    };
+    for (int k = 0; k < RING8 - 1 && k < nstage; ++k) issue(bufp(k), k);
+    wait_oldest(RING8 == 3 && nstage > 1);
     __syncthreads();
     bool fresh = first;
-    // chunks of FLUSH8 stages; stage st is in bufA (st even) or bufB, and the
-    // next stage is loaded into the other buffer while st is computed
     for (int c0 = 0; c0 < nstage; c0 += FLUSH8) {
         const int c1 = nstage < c0 + FLUSH8 ? nstage : c0 + FLUSH8;
         for (int st = c0; st < c1; ++st) {
-            uint4 *cur = (st & 1) ? bufB : bufA;
-            uint4 *nxt = (st & 1) ? bufA : bufB;
-            if (st + 1 < nstage) issue(nxt, st + 1);
-            compute(cur);
-            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            const int nx = st + RING8 - 1;
+            if (nx < nstage) issue(bufp(nx), nx);
+            compute(bufp(st));
+            wait_oldest(RING8 == 3 && st + 2 < nstage);
             __syncthreads();
         }
         flush(fresh);
@@ -701,6 +726,7 @@ __global__ void __launch_bounds__(NT8)
 k_split8_reduce(Split8Args args) {
     __shared__ uint4 bufA[BUF8];
     __shared__ uint4 bufB[BUF8];
+    __shared__ uint4 bufC[RING8 == 3 ? BUF8 : 1];
 
     int b = blockIdx.x;
     const bool isH = b < args.ntri8;
@@ -717,13 +743,13 @@ k_split8_reduce(Split8Args args) {
     double2 *out = isH ? args.H : args.S;
     if (isH) {
         const Split8Seg h0 = args.h[0], h1 = args.h[1], h2 = args.h[2];
-        split8_segment(h0, n_g, args.groups, m0, n0, true, out, bufA, bufB);
-        split8_segment(h1, n_g, args.groups, m0, n0, false, out, bufA, bufB);
-        split8_segment(h2, n_g, args.groups, m0, n0, false, out, bufA, bufB);
+        split8_segment(h0, n_g, args.groups, m0, n0, true, out, bufA, bufB, bufC);
+        split8_segment(h1, n_g, args.groups, m0, n0, false, out, bufA, bufB, bufC);
+        split8_segment(h2, n_g, args.groups, m0, n0, false, out, bufA, bufB, bufC);
     } else {
         const Split8Seg s0 = args.s[0], s1 = args.s[1];
-        split8_segment(s0, n_g, args.groups, m0, n0, true, out, bufA, bufB);
-        split8_segment(s1, n_g, args.groups, m0, n0, false, out, bufA, bufB);
+        split8_segment(s0, n_g, args.groups, m0, n0, true, out, bufA, bufB, bufC);
+        split8_segment(s1, n_g, args.groups, m0, n0, false, out, bufA, bufB, bufC);
     }
 }
 

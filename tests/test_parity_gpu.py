@@ -71,6 +71,7 @@ CASES = {
     "all_failing": lambda: make_problem(3, 9, 300, seed=7, fail_atoms=[0, 1, 2]),
     "mixed_nl": lambda: make_problem(6, [16, 49, 81, 121, 1, 128], 700, seed=8,
                                      fail_atoms=[2], planted={3: 50}),
+    "long_contraction": lambda: make_problem(260, 128, 97, seed=10, fail_atoms=[5, 200]),
 }
 
 

@@ -80,6 +80,9 @@ CASES = {
     "one_element": lambda: make_problem(1, 1, 1, seed=5),
     "zero_columns": lambda: _zero_columns(make_problem(4, 20, 300, seed=6), [0, 17, 299]),
     "wide_range": lambda: _wide_range(make_problem(6, 30, 400, seed=7, fail_atoms=[3])),
+    # K = 33280 > 32768 rows: the INT8 levels are folded into the output
+    # mid-segment (every 32768 rows) as well as at segment ends
+    "long_contraction": lambda: make_problem(260, 128, 97, seed=10, fail_atoms=[5, 200]),
 }
 
 
