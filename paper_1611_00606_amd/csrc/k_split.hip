@@ -490,20 +490,31 @@ k_split_reduce(SplitArgs args) {
 #ifndef HS_SPLIT8_BAND
 #define HS_SPLIT8_BAND 8
 #endif
+// tile rows: 64 (square 64 x 64 tiles) or 128 (128 x 64 halves of 128 x 128
+// lower-triangle super tiles)
+#ifndef HS_SPLIT8_BM
+#define HS_SPLIT8_BM 64
+#endif
 
 typedef int i4 __attribute__((ext_vector_type(4)));
 typedef unsigned short us2 __attribute__((ext_vector_type(2)));
 
 constexpr int NSL8 = 5;                  // slices per value
 constexpr int NLEV8 = 5;                 // levels c = 2 .. 6
-constexpr int B8 = 64;                   // tile rows (g') = tile cols (g)
+constexpr int B8M = HS_SPLIT8_BM;        // tile rows (g')
+constexpr int B8 = 64;                   // tile cols (g)
 constexpr int NW8 = HS_SPLIT8_WAVES;
-constexpr int W8M = 2, W8N = NW8 / 2;    // waves
+#ifndef HS_SPLIT8_WM
+#define HS_SPLIT8_WM (HS_SPLIT8_BM == 128 ? 8 : 2)
+#endif
+constexpr int W8M = HS_SPLIT8_WM, W8N = NW8 / W8M;   // waves
 constexpr int NT8 = 64 * NW8;
-constexpr int T8M = B8 / W8M / 16, T8N = B8 / W8N / 16;   // 16x16 blocks per wave
+constexpr int T8M = B8M / W8M / 16, T8N = B8 / W8N / 16;   // 16x16 blocks per wave
 constexpr int GRP8 = 4;                  // groups of 8 complex rows per stage = 32 rows
-constexpr int OP8_ITEMS = NSL8 * GRP8 * B8;   // 16-byte items per operand per stage
-constexpr int BUF8 = 2 * OP8_ITEMS;
+constexpr int P8_ITEMS = NSL8 * GRP8 * B8M;   // 16-byte items per stage
+constexpr int OP8_ITEMS = NSL8 * GRP8 * B8;
+constexpr int BUF8 = P8_ITEMS + OP8_ITEMS;
+static_assert(B8M == 64 || (B8M == 128 && NW8 == 8), "128-row tiles use 8 waves");
 constexpr int FLUSH8 = 1024;                  // stages (32768 complex rows) per flush
 constexpr int BAND8 = HS_SPLIT8_BAND;
 constexpr int RING8 = HS_SPLIT8_RING;
@@ -586,26 +597,52 @@ __device__ __forceinline__ void split8_segment(const Split8Seg sg, int n_g, int 
     const long long plane = (long long)groups * n_g;
     const int nstage = groups / GRP8;
 
-    // direct loads of stage st into buf (40 of 64 columns each): with 8 waves
-    // wave w loads group w % 4 of every slice of operand w / 4; with 4 waves
-    // group w of both operands
+    // direct loads of stage st into buf, 64 columns each. 64-row tiles (40
+    // loads): with 8 waves wave w loads group w % 4 of every slice of operand
+    // w / 4, with 4 waves group w of both operands. 128-row tiles (60
+    // loads): wave w loads group w / 2, columns 64 (w % 2) .. of every P
+    // slice, and the Q (slice, group) pairs w, w + 8, w + 16.
     constexpr int OPS_PER_WAVE = NW8 == 8 ? 1 : 2;
-    const int grp_w = wave % GRP8;
-    const int op0 = NW8 == 8 ? wave / GRP8 : 0;
-    int pc = m0 + lane;
+    constexpr int LOADS_PER_WAVE = B8M == 128 ? NSL8 + 3 : NSL8 * OPS_PER_WAVE;
+    const int grp_w = B8M == 128 ? wave >> 1 : wave % GRP8;
+    const int half_w = B8M == 128 ? wave & 1 : 0;
+    const int op0 = NW8 == 8 && B8M == 64 ? wave / GRP8 : 0;
+    int pc = m0 + half_w * 64 + lane;
     pc = pc < n_g ? pc : n_g - 1;
     int qc = n0 + lane;
     qc = qc < n_g ? qc : n_g - 1;
+    // per-lane byte offsets (32-bit) from wave-uniform row bases: the loads
+    // then take the scalar-base form and need no 64-bit address registers
+    const unsigned pvo = (unsigned)pc * 16u, qvo = (unsigned)qc * 16u;
+    auto ld = [&](const uint4 *row, unsigned vo, uint4 *dst) __attribute__((always_inline)) {
+        __builtin_amdgcn_global_load_lds(
+            reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(row) + vo), dst, 16, 0, 0);
+    };
     auto issue = [&](uint4 *buf, int st) __attribute__((always_inline)) {
-        const long long so = (long long)(st * GRP8 + grp_w) * n_g;
-#pragma unroll
-        for (int o = 0; o < OPS_PER_WAVE; ++o) {
-            const int op = op0 + o;
-            const uint4 *base = (op == 0 ? sg.P + pc : sg.Q + qc) + so;
-            uint4 *dst = buf + op * OP8_ITEMS + grp_w * B8;
+        if constexpr (B8M == 128) {
 #pragma unroll
             for (int s = 0; s < NSL8; ++s)
-                __builtin_amdgcn_global_load_lds(base + s * plane, dst + s * GRP8 * B8, 16, 0, 0);
+                ld(sg.P + s * plane + (long long)(st * GRP8 + grp_w) * n_g, pvo,
+                   buf + (s * GRP8 + grp_w) * B8M + half_w * 64);
+#pragma unroll
+            for (int it = 0; it < 3; ++it) {
+                const int j = wave + 8 * it;
+                if (j < NSL8 * GRP8) {
+                    const int s = j / GRP8, grp = j % GRP8;
+                    ld(sg.Q + s * plane + (long long)(st * GRP8 + grp) * n_g, qvo,
+                       buf + P8_ITEMS + (s * GRP8 + grp) * B8);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int o = 0; o < OPS_PER_WAVE; ++o) {
+                const int op = op0 + o;
+                const uint4 *rows = (op == 0 ? sg.P : sg.Q) + (long long)(st * GRP8 + grp_w) * n_g;
+                const unsigned vo = op == 0 ? pvo : qvo;
+                uint4 *dst = buf + op * P8_ITEMS + grp_w * B8;
+#pragma unroll
+                for (int s = 0; s < NSL8; ++s) ld(rows + s * plane, vo, dst + s * GRP8 * B8);
+            }
         }
     };
 
@@ -624,17 +661,20 @@ __device__ __forceinline__ void split8_segment(const Split8Seg sg, int n_g, int 
     const int lg = lane >> 4, lc = lane & 15;
     auto compute = [&](const uint4 *buf) __attribute__((always_inline)) {
         const uint4 *lp = buf;
-        const uint4 *lq = buf + OP8_ITEMS;
+        const uint4 *lq = buf + P8_ITEMS;
         i4 a[T8M][NSL8];
 #pragma unroll
         for (int s = 0; s < NSL8; ++s)
 #pragma unroll
             for (int i = 0; i < T8M; ++i)
-                a[i][s] = __builtin_bit_cast(i4, lp[(s * GRP8 + lg) * B8 + wm * (B8 / W8M) + i * 16 + lc]);
+                a[i][s] = __builtin_bit_cast(i4, lp[(s * GRP8 + lg) * B8M + wm * (B8M / W8M) + i * 16 + lc]);
 #pragma unroll
         for (int t = 0; t < NSL8; ++t)
 #pragma unroll
             for (int j = 0; j < T8N; ++j) {
+                // one Q fragment (and its Im form) live at a time: otherwise
+                // the scheduler hoists all of them and the accumulators spill
+                __builtin_amdgcn_sched_barrier(0);
                 const uint4 u = lq[(t * GRP8 + lg) * B8 + wn * (B8 / W8N) + j * 16 + lc];
                 const i4 b = __builtin_bit_cast(i4, u);
                 const i4 bi = i4{(int)im_pairs(u.x), (int)im_pairs(u.y), (int)im_pairs(u.z),
@@ -660,7 +700,7 @@ __device__ __forceinline__ void split8_segment(const Split8Seg sg, int n_g, int 
             for (int i = 0; i < T8M; ++i)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int gp = m0 + wm * (B8 / W8M) + i * 16 + 4 * lg + v;
+                    const int gp = m0 + wm * (B8M / W8M) + i * 16 + 4 * lg + v;
                     if (gp < n_g && g <= gp) {
                         const double w = ldexp(1.0, col_exp8(sg.mP, gp) + eq - 14);
                         double tr = (double)lre[i][j][NLEV8 - 1][v];
@@ -690,15 +730,19 @@ __device__ __forceinline__ void split8_segment(const Split8Seg sg, int n_g, int 
     // Each wave issues LOADS_PER_WAVE direct loads per stage, so waiting
     // until at most (RING8 - 2) * LOADS_PER_WAVE of them are outstanding
     // completes the oldest stage in flight.
-    constexpr int LOADS_PER_WAVE = NSL8 * OPS_PER_WAVE;
     auto bufp = [&](int st) __attribute__((always_inline)) {
         const int r = st % RING8;
         return r == 0 ? bufs0 : r == 1 ? bufs1 : bufs2;
     };
     auto wait_oldest = [&](bool more_in_flight) __attribute__((always_inline)) {
+        // with 3 buffers: at most the newest stage's loads may stay in flight
+        // (a wave issues at most LOADS_PER_WAVE per stage; fewer only waits
+        // longer)
         if (RING8 == 3 && more_in_flight) {
-            static_assert(LOADS_PER_WAVE == 5 || LOADS_PER_WAVE == 10, "waitcnt immediates");
+            static_assert(LOADS_PER_WAVE == 5 || LOADS_PER_WAVE == 8 || LOADS_PER_WAVE == 10,
+                          "waitcnt immediates");
             if constexpr (LOADS_PER_WAVE == 5) asm volatile("s_waitcnt vmcnt(5)" ::: "memory");
+            else if constexpr (LOADS_PER_WAVE == 8) asm volatile("s_waitcnt vmcnt(7)" ::: "memory");
             else asm volatile("s_waitcnt vmcnt(10)" ::: "memory");
         } else {
             asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -712,8 +756,15 @@ __device__ __forceinline__ void split8_segment(const Split8Seg sg, int n_g, int 
         const int c1 = nstage < c0 + FLUSH8 ? nstage : c0 + FLUSH8;
         for (int st = c0; st < c1; ++st) {
             const int nx = st + RING8 - 1;
-            if (nx < nstage) issue(bufp(nx), nx);
-            compute(bufp(st));
+            // the buffer being computed and the one being loaded are
+            // distinct: saying so (restrict) keeps the compiler from waiting
+            // for the direct loads before every LDS read of the stage
+            auto stage = [&](const uint4 *__restrict__ cur, uint4 *__restrict__ nxt)
+                             __attribute__((always_inline)) {
+                if (nx < nstage) issue(nxt, nx);
+                compute(cur);
+            };
+            stage(bufp(st), bufp(nx));
             wait_oldest(RING8 == 3 && st + 2 < nstage);
             __syncthreads();
         }
@@ -735,10 +786,20 @@ k_split8_reduce(Split8Args args) {
     const int t = (b % 8) * per_xcd + b / 8;
     if (t >= args.ntri) return;
     int ti, tj;
-    sband_tile(t, args.nt, ti, tj, BAND8);
-    if (ti < 0) return;
-    const int m0 = ti * B8, n0 = tj * B8;
     const int n_g = args.n_g;
+    int m0, n0;
+    if constexpr (B8M == 128) {   // t: (super tile, half)
+        sband_tile(t >> 1, args.nt, ti, tj, BAND8);
+        if (ti < 0) return;
+        m0 = ti * 128;
+        n0 = tj * 128 + (t & 1) * 64;
+        if (n0 >= n_g) return;
+    } else {
+        sband_tile(t, args.nt, ti, tj, BAND8);
+        if (ti < 0) return;
+        m0 = ti * B8;
+        n0 = tj * B8;
+    }
 
     double2 *out = isH ? args.H : args.S;
     if (isH) {
@@ -825,8 +886,8 @@ hipError_t launch_split8_reduce(int K, int n_g, const SliceView (&hseg)[3][2],
     a.S = S;
     a.n_g = n_g;
     a.groups = (K + 31) / 32 * GRP8;
-    a.nt = (n_g + B8 - 1) / B8;
-    a.ntri = a.nt * (a.nt + 1) / 2;
+    a.nt = (n_g + B8M - 1) / B8M;
+    a.ntri = a.nt * (a.nt + 1) / 2 * (B8M / B8);   // blocks per output
     a.ntri8 = (a.ntri + 7) / 8 * 8;
     hipLaunchKernelGGL(k_split8_reduce, dim3(2 * a.ntri8), dim3(NT8), 0, st, a);
     return hipGetLastError();
