@@ -55,10 +55,14 @@
 #define HS_SPLIT_FLUSH 4
 #endif
 #ifndef HS_SPLIT_WM
-#define HS_SPLIT_WM 4
+#define HS_SPLIT_WM 2
 #endif
 #ifndef HS_SPLIT_WN
-#define HS_SPLIT_WN 2
+#define HS_SPLIT_WN 4
+#endif
+// 1: slices move global -> LDS with direct 16-byte loads; 0: through registers
+#ifndef HS_SPLIT_DIRECT
+#define HS_SPLIT_DIRECT 1
 #endif
 
 namespace hs {
@@ -189,7 +193,7 @@ static_assert(SBITS1 + SBITS - 1 + 1 + ilog2(32 * FLUSH) <= 24, "level 3 exact i
 constexpr int SBAND = 8;
 // LDS per operand per stage: NSL slices x SGRP groups x 64 columns x 16 B
 constexpr int LDS_OP = NSL * SGRP * 64;   // in units of 16 B
-constexpr int LD_ITEMS = (LDS_OP + SNT - 1) / SNT;
+[[maybe_unused]] constexpr int LD_ITEMS = (LDS_OP + SNT - 1) / SNT;
 static_assert(SBM == 64 && SBN == 64, "loader assumes 64-column tiles");
 static_assert(SWTM % 16 == 0 && SWTN % 16 == 0, "wave tiling");
 
@@ -250,6 +254,28 @@ __device__ __forceinline__ void split_segment(const SplitSeg sg, int n_g, int gr
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave % SWM, wn = wave / SWM;
 
+    const long long plane = (long long)groups * n_g;   // 16-byte items per slice
+    const int nstage = groups / SGRP;
+#if HS_SPLIT_DIRECT
+    // direct global -> LDS loads, 64 columns each: wave w loads group w % 4
+    // of every slice of operand w / 4 (P for waves 0-3, Q for 4-7); columns
+    // past the edge read the last column (they only feed outputs past N_G)
+    static_assert(SNT == 512 && SGRP == 4, "direct loader assumes 8 waves, 4 groups");
+    const int grp_w = wave % SGRP, op_w = wave / SGRP;
+    int ldc = (op_w == 0 ? m0 : n0) + lane;
+    ldc = ldc < n_g ? ldc : n_g - 1;
+    const unsigned ldvo = (unsigned)ldc * 16u;
+    const uint4 *ldrows = reinterpret_cast<const uint4 *>(op_w == 0 ? sg.P : sg.Q);
+    auto issue = [&](uint4 *buf, int st) __attribute__((always_inline)) {
+        const uint4 *rows = ldrows + (long long)(st * SGRP + grp_w) * n_g;
+        uint4 *dst = buf + op_w * LDS_OP + grp_w * 64;
+#pragma unroll
+        for (int s = 0; s < NSL; ++s)
+            __builtin_amdgcn_global_load_lds(
+                reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(rows + s * plane) + ldvo),
+                dst + s * SGRP * 64, 16, 0, 0);
+    };
+#else
     // loader: NSL*SGRP*64 16-byte items per operand per stage, item
     // id -> (slice, group, column) = (id / 256, (id / 64) % 4, id % 64); each
     // thread moves up to LD_ITEMS of them (indices clamped, extra ones unused)
@@ -257,11 +283,9 @@ __device__ __forceinline__ void split_segment(const SplitSeg sg, int n_g, int gr
     const int pm = m0 + col, qn = n0 + col;
     const bool pok = pm < n_g, qok = qn < n_g;
     const int pmc = pok ? pm : n_g - 1, qnc = qok ? qn : n_g - 1;
-    const long long plane = (long long)groups * n_g;   // 16-byte items per slice
     const uint4 *Pg = reinterpret_cast<const uint4 *>(sg.P);
     const uint4 *Qg = reinterpret_cast<const uint4 *>(sg.Q);
     uint4 rp[LD_ITEMS], rq[LD_ITEMS];
-    const int nstage = groups / SGRP;
     auto fetch = [&](int st) {
         const int st_c = st < nstage ? st : nstage - 1;   // clamped (unused past the end)
 #pragma unroll
@@ -296,6 +320,7 @@ __device__ __forceinline__ void split_segment(const SplitSeg sg, int n_g, int gr
             lq[id] = b;
         }
     };
+#endif
 
     // column scales of this lane's accumulator rows (g') and columns (g),
     // with the 2^-2b1 weight of the first level folded in
@@ -347,17 +372,9 @@ __device__ __forceinline__ void split_segment(const SplitSeg sg, int n_g, int gr
         clear();
     };
 
-    clear();
-    if (nstage == 0) return;
-    fetch(0);
-    stash(0);
-    __syncthreads();
-
     const int lg = lane >> 4, lc = lane & 15;
-    for (int st = 0; st < nstage; ++st) {
-        fetch(st + 1);
-        const uint4 *lp = lds + (st & 1) * 2 * LDS_OP;
-        const uint4 *lq = lp + LDS_OP;
+    // slice products of one stage from LDS (P slices at lp, Q slices at lq)
+    auto compute = [&](const uint4 *lp, const uint4 *lq) __attribute__((always_inline)) {
         h8 a[STM][NSL], bre[STN][NSL];
 #pragma unroll
         for (int s = 0; s < NSL; ++s) {
@@ -393,10 +410,41 @@ __device__ __forceinline__ void split_segment(const SplitSeg sg, int n_g, int gr
                     }
                 }
             }
+    };
+
+    clear();
+    if (nstage == 0) return;
+#if HS_SPLIT_DIRECT
+    issue(lds, 0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    for (int st = 0; st < nstage; ++st) {
+        // the buffer being computed and the one being loaded are distinct:
+        // saying so (restrict) keeps the compiler from waiting for the direct
+        // loads before the stage's LDS reads
+        auto stage = [&](const uint4 *__restrict__ cur, uint4 *__restrict__ nxt)
+                         __attribute__((always_inline)) {
+            if (st + 1 < nstage) issue(nxt, st + 1);
+            compute(cur, cur + LDS_OP);
+        };
+        stage(lds + (st & 1) * 2 * LDS_OP, lds + ((st + 1) & 1) * 2 * LDS_OP);
+        if ((st + 1) % FLUSH == 0 || st + 1 == nstage) flush();
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+    }
+#else
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int st = 0; st < nstage; ++st) {
+        fetch(st + 1);
+        const uint4 *lp = lds + (st & 1) * 2 * LDS_OP;
+        compute(lp, lp + LDS_OP);
         stash((st + 1) & 1);
         if ((st + 1) % FLUSH == 0 || st + 1 == nstage) flush();
         __syncthreads();
     }
+#endif
 }
 
 __global__ void __launch_bounds__(SNT)
