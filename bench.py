@@ -42,7 +42,8 @@ SPLIT_I8_PER_FP64 = 15.0
 
 
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_reduce_precision_ng8000.md")
-TRAFFIC_SOURCES = ["paper_1611_00606_amd/csrc/zmfma_tile.h", "paper_1611_00606_amd/csrc/k_reduce.hip"]
+TRAFFIC_SOURCES = ["paper_1611_00606_amd/csrc/zmfma_tile.h", "paper_1611_00606_amd/csrc/zmfma_direct.h",
+                   "paper_1611_00606_amd/csrc/k_reduce.hip"]
 
 
 def measured_traffic(config: str):
