@@ -419,7 +419,7 @@ def main():
     achieved = f_red / (red_ms * 1e-3) / 1e12
 
     out = {
-        "metric": "H+S build FP64-equiv TFLOP/s (% MFMA peak)",
+        "metric": "H+S build FP64-equiv TFLOP/s (% MFMA peak); k-point builds/s + p99 latency",
         "value": round(value, 3),
         "unit": "TFLOP/s",
         "n_gpus": 1,
@@ -474,7 +474,10 @@ def main():
     if not args.no_serving:
         print("bench: serving stream", file=sys.stderr, flush=True)
         out["serving"] = serving_bench(args.seed)
+        out["kpoint_builds_per_s"] = out["serving"]["builds_per_s"]
+        out["p99_latency_ms"] = out["serving"]["p99_latency_ms"]
         if not args.no_split:
+            out["serving_split_f16"] = serving_bench(args.seed, mode=1)
             out["serving_split_i8"] = serving_bench(args.seed, mode=2)
     print(json.dumps(out), flush=True)
 
