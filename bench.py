@@ -174,7 +174,8 @@ SPLIT_MODES = {
 }
 
 
-def split_bench(p, steps: int, warmup: int, fp64_ms: float, hip, mode: int, n_cols: int = 12):
+def split_bench(p, steps: int, warmup: int, fp64_ms: float, hip, mode: int, n_cols: int = 12,
+                atom_kw=None):
     """Split-precision form on the same workload: time, speedup over the FP64
     path, and relative Frobenius error of H and of S against the CPU oracle
     on sampled columns."""
@@ -184,7 +185,7 @@ def split_bench(p, steps: int, warmup: int, fp64_ms: float, hip, mode: int, n_co
     from paper_1611_00606_amd.flops import algorithmic_flops, reduction_flops
 
     m = SPLIT_MODES[mode]
-    run = DeviceBuild.from_problem(p, device="cuda:0", mode=mode)
+    run = DeviceBuild.from_problem(p, device="cuda:0", mode=mode, **(atom_kw or {}))
     ph, total = timed_builds(run, steps, warmup, hip)
     info = run.info.cpu().numpy()
     rng = np.random.default_rng(1234)
@@ -353,6 +354,9 @@ def main():
                     help="skip the split-precision measurement")
     ap.add_argument("--split-modes", default="1,2",
                     help="split modes to measure (1 = HS_SPLIT_F16, 2 = HS_SPLIT_I8)")
+    ap.add_argument("--per-atom", choices=["batched", "separate"], default="batched",
+                    help="per-atom stage of the timed builds: the batched persistent launch with "
+                         "autotuned tile shapes, or separate preparation and product launches")
     ap.add_argument("--no-batching", action="store_true",
                     help="skip the batched per-atom stage measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -384,7 +388,13 @@ def main():
         return
     p = make_config(args.config, seed=args.seed)
     print(f"bench: config {args.config} N_A={p.N_A} N_G={p.N_G} K={p.K}", file=sys.stderr, flush=True)
-    run = DeviceBuild.from_problem(p, device="cuda:0")
+    atom_kw = {}
+    if args.per_atom == "batched":
+        # set-up, outside the timed region: tile shapes per N_L for this N_G
+        from paper_1611_00606_amd.tuning import autotune
+        tuning, _ = autotune(sorted(set(p.nl.tolist())), p.N_G, reps=3)
+        atom_kw = {"batch": 1, "tuning": tuning}
+    run = DeviceBuild.from_problem(p, device="cuda:0", **atom_kw)
     stream = torch.cuda.current_stream()
 
     for _ in range(args.warmup):
@@ -439,6 +449,9 @@ def main():
             "failing_atoms": int((info != 0).sum()), "seed": args.seed,
             "algorithmic_flops": f_alg,
         },
+        "per_atom_stage": ("batched: per-atom Cholesky and products in one persistent launch, "
+                           "autotuned tile shapes (phase 'atom_products' covers both)")
+                          if args.per_atom == "batched" else "separate launches",
         "phases_ms": {
             "prep_cholesky": round(float(ph_mean[0]), 4),
             "atom_products": round(float(ph_mean[1]), 4),
@@ -465,7 +478,7 @@ def main():
         hip = HipEvents()
         for mode in [int(m) for m in args.split_modes.split(",") if m]:
             out[SPLIT_MODES[mode]["name"]] = split_bench(p, max(3, args.steps // 2), 1, ms_step,
-                                                         hip, mode)
+                                                         hip, mode, atom_kw=atom_kw)
     if not args.no_batching:
         print("bench: batched per-atom stage", file=sys.stderr, flush=True)
         out["batching"] = batching_bench(args.seed, max(3, args.steps // 2), HipEvents())

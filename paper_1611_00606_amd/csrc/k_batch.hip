@@ -270,7 +270,12 @@ int tile_shape(int id, int *bm, int *bn) {
     return 0;
 }
 
-int default_tile(int nl) { return nl <= 32 ? 1 : nl <= 64 ? 3 : 4; }
+// Built-in choice: the 8192-output shape with the least row padding
+// (32 x 256 or 64 x 128; on a tie the taller tile).
+int default_tile(int nl) {
+    const int pad32 = (nl + 31) / 32 * 32, pad64 = (nl + 63) / 64 * 64;
+    return pad32 < pad64 ? 1 : 3;
+}
 
 void BatchPlan::make(const AtomPlan &p, int n_g, const unsigned char *cfg_table) {
     for (int v = 0; v <= HS_MAX_NL; ++v) cfg[v] = cfg_table ? cfg_table[v] : (unsigned char)default_tile(v);

@@ -34,8 +34,10 @@ def tuning_from_table(table: Dict[int, int]) -> B.hs_tuning:
 
 
 def default_shape(nl: int) -> int:
-    """The library's built-in shape id for N_L (used when no table is given)."""
-    return 1 if nl <= 32 else 3 if nl <= 64 else 4
+    """The library's built-in shape id for N_L (used when no table is given):
+    32 x 256 or 64 x 128, whichever pads the atom's rows less (ties: 64)."""
+    pad32, pad64 = -(-nl // 32) * 32, -(-nl // 64) * 64
+    return 1 if pad32 < pad64 else 3
 
 
 def autotune(nl_values: Iterable[int], n_g: int, reps: int = 3,
