@@ -366,7 +366,7 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the H/S build here is a single-GPU path "
-              "(a multi-GPU sharding is described in DESIGN.md but not built). Run with --gpus 1.",
+              "(a sharding over GPUs is designed but not built). Run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 

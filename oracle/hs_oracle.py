@@ -23,7 +23,7 @@ eye against the paper:
   * `atom_products`: the per-atom operands of Alg. 1 (Z_a of its first loop,
     Y_a / X_a of its second loop), each from its plain definition.
 
-Readings taken where the paper is silent (each listed in the design doc):
+Readings taken where the paper is silent:
   * the Cholesky factor is lower with T = C C^H (the "C_a C_a" of Sec. 2 has
     lost a conjugate-transpose; Alg. 1 then forms Y_a = C_a^H A_a);
   * a factorization fails at the first pivot d_j <= 0 or NaN, no tolerance;

@@ -1,6 +1,6 @@
 """Split-precision forms (HS_SPLIT_F16, HS_SPLIT_I8) against the CPU oracle.
 
-The tolerance is the spec one for this form: relative Frobenius error
+The tolerance for this form: relative Frobenius error
 <= 1e-9 for H and for S, each stated separately. The outputs stay exactly
 Hermitian (the lower triangle is computed and mirrored) and the Cholesky flags
 are the FP64 ones.
