@@ -132,6 +132,12 @@ def cpu_baseline(p, seconds: float):
     info = np.zeros(n, np.int32)
     info[[a for a in p.failing if a < n]] = 1
     f = algorithmic_flops(p.nl[:n], p.N_G, info)
+    # the paper's own CPU method (Alg. 1 through host BLAS/LAPACK) on the same sample
+    k = int(p.nl[:n].sum())
+    t = int((p.nl[:n].astype(np.int64) ** 2).sum())
+    t0 = time.perf_counter()
+    oracle.algorithm1(p.A[:k], p.B[:k], p.T_AA[:t], p.T_AB[:t], p.T_BB[:t], p.U[:k], p.nl[:n])
+    dt_alg1 = time.perf_counter() - t0
     return {
         "value": f / dt / 1e12,
         "unit": "TFLOP/s",
@@ -139,7 +145,69 @@ def cpu_baseline(p, seconds: float):
         "kind": "oracle",
         "sample": f"direct-sum oracle (NumPy complex128) on atoms 0..{n - 1} of {p.N_A} at full "
                   f"N_G={p.N_G}: {dt:.2f} s for {f:.3e} algorithmic flops",
+        "cpu_model": _cpu_model(),
+        "blas": _blas_vendor(),
+        "alg1_host_tflops": round(f / dt_alg1 / 1e12, 4),
+        "alg1_host_sample": f"Alg. 1 through SciPy BLAS/LAPACK (zher2k, zherk, zpotrf, ztrmm, ...) "
+                            f"on the same atoms: {dt_alg1:.2f} s",
     }
+
+
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _blas_vendor() -> str:
+    try:
+        from threadpoolctl import threadpool_info
+        libs = [f"{i.get('internal_api')} {i.get('version')}" for i in threadpool_info()
+                if i.get("user_api") == "blas"]
+        return ", ".join(sorted(set(libs))) or "unknown"
+    except Exception:
+        return "unknown"
+
+
+def atom_stage_rates(p, info, ms: float):
+    """Per-atom stage (Cholesky, T.A / T.B products): FP64 rate and HBM rate
+    against the minimum traffic (read A, B and the T blocks, write Z, W)."""
+    from paper_1611_00606_amd.flops import paper_step_flops
+    f = paper_step_flops(p.nl, p.N_G, info)
+    flops = sum(f[k] for k in ("loop1_zgemm_TBA_A", "loop1_zhemm_TBB_B", "loop2_zpotrf",
+                               "loop2_ztrmm_Y", "loop2_zhemm_X"))
+    nbytes = 16.0 * (4 * float(p.K) * p.N_G + 3 * float((p.nl.astype(np.int64) ** 2).sum()))
+    return {"ms": round(ms, 4), "tflops": round(flops / (ms * 1e-3) / 1e12, 3),
+            "frac_fp64_peak": round(flops / (ms * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS, 4),
+            "hbm_gbs": round(nbytes / (ms * 1e-3) / 1e9, 1),
+            "frac_hbm_peak": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def sync_build_wall_ms(p, reps: int = 3):
+    """Host wall time of the synchronous hs_build (allocates and frees its
+    workspace, returns after completion); uniform N_L only."""
+    import torch
+    from paper_1611_00606_amd import hs_build
+    if not np.all(p.nl == p.nl[0]):
+        return None
+    dev = torch.device("cuda:0")
+    up = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)  # noqa: E731
+    A, B, taa, tab, tbb, U = (up(x) for x in (p.A, p.B, p.T_AA, p.T_AB, p.T_BB, p.U))
+    H = torch.empty((p.N_G, p.N_G), dtype=torch.complex128, device=dev)
+    S = torch.empty_like(H)
+    hs_build(A, B, taa, tab, tbb, U, p.N_A, int(p.nl[0]), p.N_G, H, S)
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        hs_build(A, B, taa, tab, tbb, U, p.N_A, int(p.nl[0]), p.N_G, H, S)
+        ts.append(time.perf_counter() - t0)
+    del A, B, taa, tab, tbb, U, H, S
+    torch.cuda.empty_cache()
+    return round(1e3 * float(np.median(ts)), 3)
 
 
 def timed_builds(run, steps: int, warmup: int, hip):
@@ -265,7 +333,7 @@ def batching_bench(seed: int, steps: int, hip):
 
 
 def serving_bench(seed: int, n_slots: int = 4, arena_gb: float = 24.0, n_sets: int = 4,
-                  load: float = 0.8, streams: int = 3, mode: int = 0):
+                  load: float = 0.8, streams: int = 5, mode: int = 0):
     """Serving form: 64 k-point requests on one resident atom set (64 atoms,
     N_L = 64), N_G integer-uniform in [1500, 9000], Poisson arrivals at
     `load` / (mean latency of a request served alone), continuous batching
@@ -420,6 +488,7 @@ def main():
     phases = np.array([[hip.elapsed_ms(e[i], e[i + 1]) for i in range(HS_NUM_PHASE_EVENTS - 1)]
                        for e in evs])
     ph_mean = phases.mean(axis=0)
+    per_build = phases.sum(axis=1)
     hip.destroy([e for es in evs for e in es] + [t_start, t_end])
 
     f_alg = algorithmic_flops(p.nl, p.N_G, info)
@@ -458,6 +527,10 @@ def main():
             "reduce_HS": round(float(ph_mean[2]), 4),
             "mirror": round(float(ph_mean[3]), 4),
         },
+        "atom_stage": atom_stage_rates(p, info, float(ph_mean[0] + ph_mean[1])),
+        "build_ms_stats": {"median": round(float(np.median(per_build)), 3),
+                           "min": round(float(np.min(per_build)), 3),
+                           "p90": round(float(np.percentile(per_build, 90)), 3)},
         "wall_s_timed_region": round(wall, 3),
         "roofline": {
             "kernel": "k_reduce",
@@ -473,6 +546,7 @@ def main():
     }
     del run
     torch.cuda.empty_cache()
+    out["hs_build_sync_wall_ms"] = sync_build_wall_ms(p)
     if not args.no_split:
         print("bench: split precision", file=sys.stderr, flush=True)
         hip = HipEvents()
