@@ -17,3 +17,4 @@ from .hs_oracle import (  # noqa: F401
     atom_products,
 )
 from .hsdla_host import algorithm1  # noqa: F401
+from .gep import cholesky_full, gep_reduce  # noqa: F401,E402
