@@ -225,6 +225,42 @@ int hs_autotune_atoms(const int32_t *nl_values, int n_values, int N_G, int reps,
                       void *stream, hs_tuning *out, float *ms);
 
 /* ------------------------------------------------------------------------
+ * Reduction of the generalized eigenproblem to standard form, the step that
+ * follows the build: per k-point the expansion coefficients c solve
+ * H c = lambda S c with S Hermitian and generically positive definite
+ * (Sec. 1.1). With
+ *     S = L L^H   (Cholesky; L lower with a positive real diagonal)
+ *     Ht = L^{-1} H L^{-H}
+ * H c = lambda S c holds exactly when Ht y = lambda y with y = L^H c.
+ * Blocked (panels of 64) on the complex FP64 MFMA tiles.
+ * ---------------------------------------------------------------------- */
+
+/* Device scratch hs_gep_reduce needs for N (0 for N < 1): 2 N^2 complex. */
+size_t hs_gep_workspace_bytes(int N);
+
+/*
+ * hs_gep_reduce - enqueue the reduction on `stream` (NULL: default stream)
+ * and return (asynchronous, like hs_build_ex).
+ *   1 H   device [N][N], Hermitian, read in full (an hs_build output)
+ *   2 S   device [N][N], Hermitian, only its lower triangle is read
+ *   3 N   >= 1
+ *   4 L   device [N][N] out: the Cholesky factor, upper triangle zero
+ *   5 Ht  device [N][N] out: L^{-1} H L^{-H}, exactly Hermitian with a
+ *         real diagonal (its lower triangle mirrored)
+ *   6 info  device int32 or NULL: 0, or the 1-based index of the first
+ *         pivot of S that is not > 0 or is NaN (LAPACK zpotrf); L and Ht
+ *         are undefined then
+ *   7 workspace  device, >= hs_gep_workspace_bytes(N) bytes, 256-byte
+ *         aligned;  8 workspace_bytes;  9 stream
+ * Outputs must not overlap the inputs or each other. Returns 0, -i for an
+ * invalid argument i (NULL pointer, N < 1), 2 (workspace too small), or 1
+ * (HIP error).
+ */
+int hs_gep_reduce(const hs_complex *H, const hs_complex *S, int N,
+                  hs_complex *L, hs_complex *Ht, int32_t *info,
+                  void *workspace, size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * Resident context: one atom set, many k-points.
  *
  * T^[..]_a and U_a do not depend on the k-point, while A_a, B_a do: there is

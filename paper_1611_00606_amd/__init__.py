@@ -46,5 +46,7 @@ from ._binding import (  # noqa: F401,E402
     hs_server_destroy,
     hs_tile_config,
     hs_autotune_atoms,
+    hs_gep_workspace_bytes,
+    hs_gep_reduce,
 )
 from .runner import DeviceBuild  # noqa: F401,E402

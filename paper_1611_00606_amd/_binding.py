@@ -144,6 +144,10 @@ def load_library() -> ctypes.CDLL:
     lib.hs_autotune_atoms.argtypes = [i32p, i32, i32, i32, vp, ctypes.POINTER(hs_tuning),
                                       ctypes.POINTER(ctypes.c_float)]
     lib.hs_autotune_atoms.restype = i32
+    lib.hs_gep_workspace_bytes.argtypes = [i32]
+    lib.hs_gep_workspace_bytes.restype = sz
+    lib.hs_gep_reduce.argtypes = [vp, vp, i32, vp, vp, vp, vp, sz, vp]
+    lib.hs_gep_reduce.restype = i32
     _lib = lib
     return lib
 
@@ -392,3 +396,30 @@ def hs_autotune_atoms(nl_values, N_G, reps=3, stream=None):
         ms.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
     _raise(rc, True)
     return out, ms[: vals.size]
+
+
+# ---------------------------------------------------------------------------
+# Generalized eigenproblem reduction
+
+
+def hs_gep_workspace_bytes(N) -> int:
+    return int(load_library().hs_gep_workspace_bytes(int(N)))
+
+
+def hs_gep_reduce(H, S, L, Ht, *, info=None, workspace=None, stream=None, check=True) -> int:
+    """S = L L^H, Ht = L^-1 H L^-H on `stream` (asynchronous). H, S, L, Ht:
+    complex128 device tensors [N][N]; info: int32 device tensor [1] or None;
+    workspace: uint8 device tensor (allocated here when None)."""
+    import torch
+    _check_c128(H, S, L, Ht)
+    N = int(H.shape[0])
+    for t in (H, S, L, Ht):
+        if tuple(t.shape) != (N, N) or not t.is_contiguous() or t.device != H.device:
+            raise ValueError("H, S, L, Ht must be contiguous [N][N] tensors on one device")
+    if workspace is None:
+        workspace = torch.empty(hs_gep_workspace_bytes(N), dtype=torch.uint8, device=H.device)
+    if info is not None and info.dtype != torch.int32:
+        raise ValueError("info must be int32")
+    rc = load_library().hs_gep_reduce(_ptr(H), _ptr(S), N, _ptr(L), _ptr(Ht), _ptr(info),
+                                      _ptr(workspace), workspace.numel(), _stream_handle(stream))
+    return _raise(rc, check)

@@ -381,6 +381,24 @@ int hs_build(const hs_complex *A, const hs_complex *B, const hs_complex *T_AA,
 
 int hs_tile_config(int id, int *bm, int *bn) { return hs::tile_shape(id, bm, bn); }
 
+size_t hs_gep_workspace_bytes(int N) { return N < 1 ? 0 : hs::gep_workspace_bytes(N); }
+
+int hs_gep_reduce(const hs_complex *H, const hs_complex *S, int N, hs_complex *L, hs_complex *Ht,
+                  int32_t *info, void *workspace, size_t workspace_bytes, void *stream) {
+    if (!H) return -1;
+    if (!S) return -2;
+    if (N < 1) return -3;
+    if (!L) return -4;
+    if (!Ht) return -5;
+    if (!workspace) return -7;
+    int rc = hs::check_device();
+    if (rc != HS_OK) return rc;
+    if (workspace_bytes < hs::gep_workspace_bytes(N)) return HS_ERR_WORKSPACE;
+    hipError_t e = hs::launch_gep(c2(H), c2(S), N, c2(L), c2(Ht), info,
+                                  static_cast<char *>(workspace), static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HS_OK : hs::hip_fail(e, "hs_gep_reduce launch");
+}
+
 const char *hs_status_string(int status) {
     const std::string &m = hs::last_error();
     switch (status) {

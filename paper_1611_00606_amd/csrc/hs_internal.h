@@ -92,8 +92,15 @@ hipError_t launch_split8_reduce(int K, int n_g, const SliceView (&hseg)[3][2],
 inline size_t slice_bytes(int mode, int K, int n_g) {
     return mode == HS_SPLIT_I8 ? split8_slice_bytes(K, n_g) : split_slice_bytes(K, n_g);
 }
-// upper := conj(lower), Im(diag) := 0 for both outputs
+// upper := conj(lower), Im(diag) := 0 for both outputs (launch_mirror1: one matrix)
 hipError_t launch_mirror(double2 *H, double2 *S, int n_g, hipStream_t st);
+hipError_t launch_mirror1(double2 *M, int n, hipStream_t st);
+
+// Generalized eigenproblem reduction (k_gep.hip): S = L L^H, Ht = L^-1 H L^-H.
+// info: device int or NULL (a workspace slot is used then).
+size_t gep_workspace_bytes(int N);
+hipError_t launch_gep(const double2 *H, const double2 *S, int N, double2 *L, double2 *Ht,
+                      int *info, char *ws, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Host-side plan of one atom set and the enqueue steps shared by the one-shot

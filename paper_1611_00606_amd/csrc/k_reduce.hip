@@ -235,4 +235,10 @@ hipError_t launch_mirror(double2 *H, double2 *S, int n_g, hipStream_t st) {
     return hipGetLastError();
 }
 
+hipError_t launch_mirror1(double2 *M, int n, hipStream_t st) {
+    const int mt = (n + MT - 1) / MT;
+    hipLaunchKernelGGL(k_mirror, dim3(mt, mt, 1), dim3(256), 0, st, M, M, n);
+    return hipGetLastError();
+}
+
 }  // namespace hs

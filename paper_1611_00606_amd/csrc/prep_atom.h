@@ -9,12 +9,9 @@
 //
 // The lower triangle of T^AA_a is held packed (row-major lower, element (i,k)
 // at i(i+1)/2 + k) in LDS: for N_L = 128 that is 8256 complex values =
-// 129 KiB, inside gfx950's 160 KiB of LDS per CU. The factorization is
-// right-looking: at step j the pivot d_j = T_jj - sum_{k<j} |C_jk|^2 has
-// already been accumulated into the diagonal entry, the column below it is
-// divided by sqrt(d_j), and the trailing lower triangle receives the rank-1
-// update -C_ij conj(C_kj). A pivot that is not > 0 (NaN included) stops the
-// factorization and sets info = j+1, the LAPACK zpotrf convention.
+// 129 KiB, inside gfx950's 160 KiB of LDS per CU. The factorization
+// (chol_packed) is right-looking; a pivot that is not > 0 (NaN included)
+// stops it and sets info = j+1, the LAPACK zpotrf convention.
 #pragma once
 
 #include "hs_internal.h"
@@ -59,6 +56,52 @@ __device__ __forceinline__ void hermitian_from_lower(const double2 *__restrict__
     }
 }
 
+// Right-looking Cholesky of the packed lower triangle L (n x n, element
+// (i,k) at pidx(i,k)) in LDS by one block of NT threads (every thread calls
+// it). At step j the pivot d_j = T_jj - sum_{k<j} |C_jk|^2 has already been
+// accumulated into the diagonal entry; the column below it is divided by
+// sqrt(d_j) and the trailing triangle receives -C_ij conj(C_kj). On return
+// the entries below the diagonal hold C, diag[j] = C_jj, and the result is
+// 0 or the 1-based index of the first pivot that is not > 0 (NaN included),
+// at which the factorization stopped.
+template <int NT>
+__device__ __forceinline__ int chol_packed(double2 *L, double *diag, int n) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    constexpr int NW = NT / 64;
+    int info = 0;
+    for (int j = 0; j < n; ++j) {
+        const double dj = L[pidx(j, j)].x;
+        if (!(dj > 0.0)) {
+            info = j + 1;
+            break;
+        }
+        const double cjj = sqrt(dj);
+        if (tid == 0) diag[j] = cjj;
+        for (int i = j + 1 + tid; i < n; i += NT) {
+            double2 v = L[pidx(i, j)];
+            v.x /= cjj;
+            v.y /= cjj;
+            L[pidx(i, j)] = v;
+        }
+        __syncthreads();
+        for (int i = j + 1 + wave; i < n; i += NW) {
+            const double2 cij = L[pidx(i, j)];
+            for (int k = j + 1 + lane; k <= i; k += 64) {
+                const double2 ckj = L[pidx(k, j)];
+                double2 t = L[pidx(i, k)];
+                // t -= cij * conj(ckj)
+                t.x -= cij.x * ckj.x + cij.y * ckj.y;
+                t.y -= cij.y * ckj.x - cij.x * ckj.y;
+                L[pidx(i, k)] = t;
+            }
+        }
+        __syncthreads();
+    }
+    return info;
+}
+
 // Preparation of atom a by one block of NT threads (every thread calls it):
 //   M2_a = 1/2 T_BB,a (Hermitian), d, sel[0..2K) rows of a; then *flag_m2
 //   (if not null) is set;
@@ -77,9 +120,6 @@ __device__ __forceinline__ void prep_atom(const Atoms &at, int a, const double2 
     double *diag = reinterpret_cast<double *>(lds + PACKED_MAX * 16);
 
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    constexpr int NW = NT / 64;
 
     const int r0 = at.row_off[a];
     const int n = at.row_off[a + 1] - r0;
@@ -118,35 +158,7 @@ __device__ __forceinline__ void prep_atom(const Atoms &at, int a, const double2 
     }
     __syncthreads();
 
-    int info = 0;
-    for (int j = 0; j < n; ++j) {
-        const double dj = L[pidx(j, j)].x;
-        if (!(dj > 0.0)) {
-            info = j + 1;
-            break;
-        }
-        const double cjj = sqrt(dj);
-        if (tid == 0) diag[j] = cjj;
-        for (int i = j + 1 + tid; i < n; i += NT) {
-            double2 v = L[pidx(i, j)];
-            v.x /= cjj;
-            v.y /= cjj;
-            L[pidx(i, j)] = v;
-        }
-        __syncthreads();
-        for (int i = j + 1 + wave; i < n; i += NW) {
-            const double2 cij = L[pidx(i, j)];
-            for (int k = j + 1 + lane; k <= i; k += 64) {
-                const double2 ckj = L[pidx(k, j)];
-                double2 t = L[pidx(i, k)];
-                // t -= cij * conj(ckj)
-                t.x -= cij.x * ckj.x + cij.y * ckj.y;
-                t.y -= cij.y * ckj.x - cij.x * ckj.y;
-                L[pidx(i, k)] = t;
-            }
-        }
-        __syncthreads();
-    }
+    const int info = chol_packed<NT>(L, diag, n);
 
     double2 *m1 = M1 + t0;
     if (info == 0) {

@@ -201,3 +201,14 @@ def test_autotune_argument_checks():
     assert lib.hs_autotune_atoms(vp, 2, 0, 1, None, ctypes.byref(t), None) == -3
     assert lib.hs_autotune_atoms(vp, 2, 100, 0, None, ctypes.byref(t), None) == -4
     assert lib.hs_autotune_atoms(vp, 2, 100, 1, None, None, None) == -6
+
+
+def test_gep_argument_checks():
+    lib = P.load_library()
+    assert P.hs_gep_workspace_bytes(0) == 0
+    assert P.hs_gep_workspace_bytes(100) >= 2 * 16 * 100 * 100
+    args = [FAKE, FAKE, 8, FAKE, FAKE, None, FAKE, 1 << 20, None]
+    for pos, bad in ((0, None), (1, None), (2, 0), (3, None), (4, None), (6, None)):
+        a = list(args)
+        a[pos] = bad
+        assert lib.hs_gep_reduce(*a) == -(pos + 1)
