@@ -232,10 +232,11 @@ int hs_autotune_atoms(const int32_t *nl_values, int n_values, int N_G, int reps,
  *     S = L L^H   (Cholesky; L lower with a positive real diagonal)
  *     Ht = L^{-1} H L^{-H}
  * H c = lambda S c holds exactly when Ht y = lambda y with y = L^H c.
- * Blocked (panels of 64) on the complex FP64 MFMA tiles.
+ * Recursive, with 64 x 64 leaves; the O(N^3) work runs as products on the
+ * complex FP64 MFMA tiles.
  * ---------------------------------------------------------------------- */
 
-/* Device scratch hs_gep_reduce needs for N (0 for N < 1): 2 N^2 complex. */
+/* Device scratch hs_gep_reduce needs for N (0 for N < 1): 4 N^2 complex. */
 size_t hs_gep_workspace_bytes(int N);
 
 /*

@@ -2,185 +2,113 @@
 // standard form, the step after the build:
 //     S = L L^H  (L lower, positive real diagonal),   Ht = L^{-1} H L^{-H}.
 //
-// Blocked in panels of NB = 64 columns/rows, the O(N^3) work on the complex
-// FP64 MFMA tile engine (zmfma_tile.h):
-//   Cholesky, per panel k (rows/cols kb .. kb+nb):
-//     k_gep_chol_diag   factor the diagonal block in LDS (chol_packed)
-//     k_gep_trsm (0)    panel rows below: L_ik = S_ik L_kk^{-H}, stored both
-//                       in L and, conjugate-transposed, in LH = L^H
-//     k_gep_update      trailing lower triangle: S_ij -= L_ik L_jk^H
-//   X = L^{-1} H, then Ht = L^{-1} X^H (= L^{-1} H L^{-H} for Hermitian H),
-//   each a blocked forward substitution, per panel k:
-//     k_gep_trsm (1)    X_k = L_kk^{-1} X_k (rows kb .. kb+nb, all columns)
-//     k_gep_update      X_i -= L_ik X_k for the rows below
-//   k_gep_conj_t        X^H between the two substitutions
-//   mirror              Ht := lower(Ht) + its conjugate transpose (exactly
-//                       Hermitian, real diagonal)
-// The updates read L's panel columns as rows of LH, which is the
-// contraction-by-rows layout the tile engine takes, so no update needs a
-// transposed operand.
+// The O(N^3) work runs as products on the complex FP64 MFMA tile engine with
+// direct global -> LDS loads (zmfma_direct.h):
+//   factor, right-looking over panels of LB = 128 columns:
+//     k_gep_leaf                        Cholesky of the diagonal block and the
+//                                       inverse M11 = L11^{-1} (one workgroup)
+//     LH21 = M11 S21^H                  (= L21^H, the panel)
+//     S22 -= L21 L21^H                  lower triangle, contraction over 128
+//   invert, recursive over the same blocks (split at m):
+//     M21 = -M22 (L21 M11)              M = L^{-1}
+//   then, with MH = M^H = L^{-H} (upper triangular),
+//     V  = H MH                         (= (L^{-1} H)^H for Hermitian H)
+//     Ht = V^H MH                       lower triangle, then mirrored
+//
+// Work: N^3/3 complex multiply-adds for the factor and its inverse, N^3/2
+// for V, N^3/6 for the lower triangle of Ht (triangular operands skip their
+// zero blocks), N^3 in all = 8 N^3 real flops, against 7/6 N^3 (9.33 N^3) for
+// the Cholesky and two full triangular solves of the plain definition. The
+// explicit inverse of L is the usual choice for this reduction in FLAPW
+// eigensolvers; its error grows with cond(L) = cond(S)^{1/2} like that of
+// the substitutions.
+//
+// Storage (all N x N row-major complex): L (output; working copy of S's
+// lower triangle during the factorization), LH (panels L21^H), M = L^{-1}
+// and MH = L^{-H} (zero outside their triangles), W (S21^H, L21 M11, then
+// V), Ht (output).
 #include "hs_internal.h"
-#include "prep_atom.h"
+#include "zmfma_direct.h"
 #include "zmfma_tile.h"
 
 namespace hs {
 
 namespace {
 
-constexpr int GNB = 64;           // panel width
-constexpr int GT = 256;           // threads of the small kernels
-using GepCfg = TileCfg<128, 128, 16, 2, 4>;
+using MmCfg = TileCfg<128, 128, 16, 2, 4>;
 
-__global__ void k_gep_info_clear(int *info) { *info = 0; }
+// product flags
+constexpr int MM_PU = 1;      // P upper triangular: k <= row of C
+constexpr int MM_QL = 2;      // Q lower triangular: k >= column of C
+constexpr int MM_QU = 4;      // Q upper triangular: k <= column of C
+constexpr int MM_LOWER = 8;   // only C's lower triangle (square region)
+// epilogue
+constexpr int OP_STORE = 0, OP_NEG = 1, OP_SUB = 2;
 
-// L := lower(S) (upper zero), X := H
-__global__ void __launch_bounds__(256)
-k_gep_init(const double2 *__restrict__ H, const double2 *__restrict__ S, double2 *__restrict__ L,
-           double2 *__restrict__ X, int N) {
-    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (e >= (long long)N * N) return;
-    const int i = (int)(e / N), j = (int)(e % N);
-    L[e] = j <= i ? S[e] : double2{0.0, 0.0};
-    X[e] = H[e];
-}
+struct MmArgs {
+    const double2 *P, *Q;
+    double2 *C;
+    int N;                    // leading dimension of P, Q, C
+    int i0, i1, j0, j1;       // C rows (P columns), C columns (Q columns)
+    int k0, k1;               // contraction rows of P and Q
+    int ntr, ntc;             // tile rows / columns of the rectangle
+    int flags, op;
+};
 
-// Cholesky of the diagonal block (rows/cols kb .. kb+nb of L) in place.
-__global__ void __launch_bounds__(GT)
-k_gep_chol_diag(double2 *__restrict__ L, int N, int kb, int nb, int *__restrict__ info) {
-    __shared__ double2 P[GNB * (GNB + 1) / 2];
-    __shared__ double diag[GNB];
-    const int tid = threadIdx.x;
-    for (int e = tid; e < nb * nb; e += GT) {
-        const int r = e / nb, c = e % nb;
-        if (c <= r) P[pidx(r, c)] = L[(long long)(kb + r) * N + kb + c];
-    }
-    __syncthreads();
-    const int inf = chol_packed<GT>(P, diag, nb);
-    for (int e = tid; e < nb * nb; e += GT) {
-        const int r = e / nb, c = e % nb;
-        if (c < r) L[(long long)(kb + r) * N + kb + c] = P[pidx(r, c)];
-        else if (c == r) L[(long long)(kb + r) * N + kb + c] = double2{diag[r], 0.0};
-    }
-    if (tid == 0 && inf != 0 && *info == 0) *info = kb + inf;
-}
-
-// Forward substitution with the diagonal block L_kk on 64 right-hand-side
-// columns per block.
-//   mode 0 (Cholesky panel): column i = t0 + .. of the RHS is conj(L[i][kb..]),
-//          the solution x gives LH[kb + c][i] = x_c and L[i][kb + c] = conj(x_c);
-//   mode 1 (substitution): column j of the RHS is X[kb..][j], overwritten.
-__global__ void __launch_bounds__(GT)
-k_gep_trsm(double2 *__restrict__ L, double2 *__restrict__ LH, double2 *__restrict__ X, int N,
-           int kb, int nb, int mode) {
-    __shared__ double2 P[GNB * (GNB + 1) / 2];
-    __shared__ double2 Y[GNB][GNB];   // [row c][RHS column]
-    const int tid = threadIdx.x;
-    const int t0 = kb + nb;
-    const int base = (mode == 0 ? t0 : 0) + blockIdx.x * GNB;   // first RHS column
-    for (int e = tid; e < nb * nb; e += GT) {
-        const int r = e / nb, c = e % nb;
-        if (c <= r) P[pidx(r, c)] = L[(long long)(kb + r) * N + kb + c];
-    }
-    if (mode == 0) {
-        for (int e = tid; e < GNB * GNB; e += GT) {   // consecutive c per row
-            const int col = e / GNB, c = e % GNB;
-            const int i = base + col;
-            double2 v = {0.0, 0.0};
-            if (i < N && c < nb) {
-                v = L[(long long)i * N + kb + c];
-                v.y = -v.y;
-            }
-            Y[c][col] = v;
-        }
-    } else {
-        for (int e = tid; e < GNB * GNB; e += GT) {   // consecutive columns per row
-            const int c = e / GNB, col = e % GNB;
-            const int j = base + col;
-            Y[c][col] = (j < N && c < nb) ? X[(long long)(kb + c) * N + j] : double2{0.0, 0.0};
-        }
-    }
-    __syncthreads();
-    const int col = tid % GNB, rg = tid / GNB;
-    for (int j = 0; j < nb; ++j) {
-        if (tid < GNB) {
-            const double d = P[pidx(j, j)].x;
-            Y[j][col].x /= d;
-            Y[j][col].y /= d;
-        }
-        __syncthreads();
-        const double2 xj = Y[j][col];
-        for (int r = j + 1 + rg; r < nb; r += GT / GNB) {
-            const double2 l = P[pidx(r, j)];
-            double2 y = Y[r][col];
-            y.x -= l.x * xj.x - l.y * xj.y;
-            y.y -= l.x * xj.y + l.y * xj.x;
-            Y[r][col] = y;
-        }
-        __syncthreads();
-    }
-    if (mode == 0) {
-        for (int e = tid; e < GNB * GNB; e += GT) {
-            const int c = e / GNB, cl = e % GNB;
-            const int i = base + cl;
-            if (i < N && c < nb) LH[(long long)(kb + c) * N + i] = Y[c][cl];
-        }
-        for (int e = tid; e < GNB * GNB; e += GT) {
-            const int cl = e / GNB, c = e % GNB;
-            const int i = base + cl;
-            if (i < N && c < nb) {
-                double2 v = Y[c][cl];
-                v.y = -v.y;
-                L[(long long)i * N + kb + c] = v;
-            }
-        }
-    } else {
-        for (int e = tid; e < GNB * GNB; e += GT) {
-            const int c = e / GNB, cl = e % GNB;
-            const int j = base + cl;
-            if (j < N && c < nb) X[(long long)(kb + c) * N + j] = Y[c][cl];
-        }
-    }
-}
-
-// C[i][j] -= sum_{c < nb} conj(P[c][i]) Q[c][j], P = rows kb .. of LH, Q =
-// rows kb .. of Qm (LH itself for the Cholesky update, X for a
-// substitution; C may be Qm: the rows read and written are disjoint), for
-// i >= t0; lower: only t0 <= j <= i (tiles of the trailing lower triangle),
-// else the whole rectangle [t0, N) x [0, N).
-__global__ void __launch_bounds__(GepCfg::NT)
-k_gep_update(const double2 *LH, const double2 *Qm, double2 *C, int N, int kb, int nb, int lower,
-             int ntc) {
-    using Cfg = GepCfg;
+// C[i][j] (op)= sum_k conj(P[k][i]) Q[k][j] over the rectangle, in absolute
+// indices; the triangular flags trim each tile's contraction range to the
+// rows where both operands can be nonzero.
+__global__ void __launch_bounds__(MmCfg::NT) k_gep_mm(const MmArgs args) {
+    using Cfg = MmCfg;
     __shared__ double2 lds[Cfg::LDS_ELEMS];
-    const int t0 = kb + nb;
+    const int flags = args.flags;
+    const int N = args.N;
+    // Tiles whose contraction is longest go first (the triangular flags
+    // make it depend on the tile row or column).
     int ti, tj;
-    if (lower) {   // blockIdx.x -> (ti, tj), tj <= ti, row-major lower triangle
-        const int t = blockIdx.x;
+    const int bid = blockIdx.x;
+    if (flags & MM_LOWER) {   // reversed row-major lower triangle: tj <= ti
+        const int t = gridDim.x - 1 - bid;
         int r = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
         while ((r + 1) * (r + 2) / 2 <= t) ++r;
         while (r * (r + 1) / 2 > t) --r;
         ti = r;
         tj = t - r * (r + 1) / 2;
-    } else {
-        ti = blockIdx.x / ntc;
-        tj = blockIdx.x % ntc;
+    } else if (flags & MM_PU) {   // longest: last tile rows
+        ti = args.ntr - 1 - bid / args.ntc;
+        tj = bid % args.ntc;
+    } else if (flags & MM_QU) {   // longest: last tile columns
+        tj = args.ntc - 1 - bid / args.ntr;
+        ti = bid % args.ntr;
+    } else {                      // MM_QL: first tile columns
+        tj = bid / args.ntr;
+        ti = bid % args.ntr;
     }
-    const int m0 = t0 + ti * Cfg::BM;
-    const int n0 = (lower ? t0 : 0) + tj * Cfg::BN;
-    if (m0 >= N || n0 >= N) return;
+    const int m0 = args.i0 + ti * Cfg::BM;
+    const int n0 = args.j0 + tj * Cfg::BN;
+    const int i1 = args.i1, j1 = args.j1;
+    if (m0 >= i1 || n0 >= j1) return;
+    int klo = args.k0, khi = args.k1;
+    if (flags & MM_PU) khi = min(khi, m0 + Cfg::BM);
+    if (flags & MM_QU) khi = min(khi, n0 + Cfg::BN);
+    if (flags & MM_QL) klo = max(klo, n0);
 
     Segs<1, false, false> t;
     t.nseg = 1;
-    t.len = nb;
+    t.len = khi > klo ? khi - klo : 0;
     t.ldp = N;
     t.ldq = N;
-    t.P[0] = LH + (long long)kb * N;
-    t.Q[0] = Qm + (long long)kb * N;
+    t.P[0] = args.P + (long long)(t.len ? klo : 0) * N;
+    t.Q[0] = args.Q + (long long)(t.len ? klo : 0) * N;
     t.palt = nullptr;
     t.sel = nullptr;
     t.qscale = nullptr;
     Acc<Cfg> acc;
-    ztile_run<Cfg>(t, m0, N, n0, N, acc, lds);
+    ztile_direct<Cfg>(t, m0, i1, n0, j1, acc, lds);
+
+    const bool lower = flags & MM_LOWER;
+    const int op = args.op;
+    double2 *C = args.C;
 #pragma unroll
     for (int i = 0; i < Cfg::TM; ++i)
 #pragma unroll
@@ -189,96 +117,422 @@ k_gep_update(const double2 *LH, const double2 *Qm, double2 *C, int N, int kb, in
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int gp = m0 + acc_row<Cfg>(i, v);
-                if (gp < N && g < N && (!lower || g <= gp)) {
+                if (gp < i1 && g < j1 && (!lower || g <= gp)) {
                     double2 *o = C + (long long)gp * N + g;
-                    double2 r = *o;
-                    r.x -= acc.re[i][j][v];
-                    r.y -= acc.im[i][j][v];
-                    *o = r;
+                    const double re = acc.re[i][j][v], im = acc.im[i][j][v];
+                    if (op == OP_SUB) {
+                        double2 r = *o;
+                        r.x -= re;
+                        r.y -= im;
+                        *o = r;
+                    } else if (op == OP_NEG) {
+                        *o = double2{-re, -im};
+                    } else {
+                        *o = double2{re, im};
+                    }
                 }
             }
         }
 }
 
-// Y = X^H through 32 x 32 LDS tiles
-__global__ void __launch_bounds__(256)
-k_gep_conj_t(const double2 *__restrict__ X, double2 *__restrict__ Y, int N) {
-    __shared__ double2 tile[32][33];
-    const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
-    const int bx = blockIdx.x, by = blockIdx.y;   // source tile rows by, cols bx
-    for (int r = ty; r < 32; r += 8) {
-        const int gr = by * 32 + r, gc = bx * 32 + tx;
-        if (gr < N && gc < N) tile[r][tx] = X[(long long)gr * N + gc];
+// Leaf: Cholesky of the diagonal block [kb, kb + nb) (nb <= LB = 128) of the
+// working matrix (lower triangle in L) and the inverse of the factor, by one
+// workgroup of 8 waves. The block, padded to 128 x 128 with the identity,
+// sits in LDS as the 36 lower 16 x 16 tiles (rows XOR-swizzled, so that the
+// MFMA fragment loads and the accumulator stores hit distinct banks).
+//   factor, right-looking over 16-column panels P:
+//     wave 0: Cholesky of the diagonal tile and its inverse, in registers
+//             (lane r holds row r; values broadcast with readlane);
+//     panel:  L_IP = C_IP inv(L_PP)^H          one tile per wave, MFMA;
+//     update: C_IJ -= L_IP L_JP^H, P < J <= I   tiles spread over the waves.
+//   inverse X = L^{-1}, in place: every wave inverts one diagonal tile, then
+//     for block rows I = 1..7: X_IJ = -X_II sum_{J<=K<I} L_IK X_KJ, J < I.
+// A pivot that is not > 0 (NaN included) records kb + j + 1 in *info unless an
+// earlier block failed (the outputs are undefined then). Writes the block of
+// L, of M = X (lower) and of MH = X^H (upper).
+constexpr int LB = 128;
+constexpr int LT = LB / 16;               // tiles per side
+constexpr int LNT = LT * (LT + 1) / 2;    // lower tiles
+
+__device__ __forceinline__ double2 *ltile(double2 *T, int I, int K) {
+    return T + (I * (I + 1) / 2 + K) * 256;
+}
+__device__ __forceinline__ int lsw(int a, int b) { return a * 16 + (b ^ a); }
+
+// value of v in lane `src` (wave-uniform src)
+__device__ __forceinline__ double bcast(double v, int src) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)u, src);
+    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Lanes 0..15 hold the rows of a 16 x 16 Hermitian tile (lower triangle
+// used); on return the rows of its Cholesky factor. Returns 0 or the
+// 1-based index of the first pivot that is not > 0.
+__device__ __forceinline__ int chol16(double2 (&a)[16], int lane) {
+    int inf = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const double d = bcast(a[j].x, j);
+        if (!(d > 0.0) && inf == 0) inf = j + 1;
+        const double c = sqrt(d);
+        const double rc = 1.0 / c;
+        a[j] = lane == j ? double2{c, 0.0} : double2{a[j].x * rc, a[j].y * rc};
+#pragma unroll
+        for (int k = j + 1; k < 16; ++k) {   // a_rk -= l_rj conj(l_kj)
+            const double lx = bcast(a[j].x, k), ly = bcast(a[j].y, k);
+            a[k].x -= a[j].x * lx + a[j].y * ly;
+            a[k].y -= a[j].y * lx - a[j].x * ly;
+        }
+    }
+    return inf;
+}
+
+// Lanes 0..15 hold the rows of a lower-triangular 16 x 16 factor; lane c
+// gets column c of its inverse (x_i = (delta_ic - sum_{k<i} l_ik x_k) / l_ii).
+__device__ __forceinline__ void inv16(const double2 (&a)[16], double2 (&x)[16], int lane) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        double2 t = double2{lane == i ? 1.0 : 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < i; ++k) {
+            const double lx = bcast(a[k].x, i), ly = bcast(a[k].y, i);   // l_ik
+            t.x -= lx * x[k].x - ly * x[k].y;
+            t.y -= lx * x[k].y + ly * x[k].x;
+        }
+        const double d = bcast(a[i].x, i);
+        x[i] = double2{t.x / d, t.y / d};
+    }
+}
+
+struct Cacc {
+    v4d re, im;
+};
+
+// c += A B^H for 16 x 16 tiles (c[i][j] += sum_k A[i][k] conj(B[j][k]))
+__device__ __forceinline__ void mma_abh(Cacc &c, const double2 *A, const double2 *B, int lane) {
+#pragma unroll
+    for (int k0 = 0; k0 < 16; k0 += 4) {
+        const double2 x = A[lsw(lane & 15, k0 + (lane >> 4))];
+        const double2 y = B[lsw(lane & 15, k0 + (lane >> 4))];
+        c.re = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x, y.x, c.re, 0, 0, 0);
+        c.re = __builtin_amdgcn_mfma_f64_16x16x4f64(x.y, y.y, c.re, 0, 0, 0);
+        c.im = __builtin_amdgcn_mfma_f64_16x16x4f64(x.y, y.x, c.im, 0, 0, 0);
+        c.im = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x, -y.y, c.im, 0, 0, 0);
+    }
+}
+
+// c += A B for 16 x 16 tiles
+__device__ __forceinline__ void mma_ab(Cacc &c, const double2 *A, const double2 *B, int lane) {
+#pragma unroll
+    for (int k0 = 0; k0 < 16; k0 += 4) {
+        const double2 x = A[lsw(lane & 15, k0 + (lane >> 4))];
+        const double2 y = B[lsw(k0 + (lane >> 4), lane & 15)];
+        c.re = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x, y.x, c.re, 0, 0, 0);
+        c.re = __builtin_amdgcn_mfma_f64_16x16x4f64(x.y, -y.y, c.re, 0, 0, 0);
+        c.im = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x, y.y, c.im, 0, 0, 0);
+        c.im = __builtin_amdgcn_mfma_f64_16x16x4f64(x.y, y.x, c.im, 0, 0, 0);
+    }
+}
+
+__device__ __forceinline__ void acc_zero(Cacc &c) {
+    c.re = v4d{0.0, 0.0, 0.0, 0.0};
+    c.im = v4d{0.0, 0.0, 0.0, 0.0};
+}
+
+// lower-triangle tile t of an n x n tile grid -> (i, j), j <= i
+__device__ __forceinline__ void tri_decode(int t, int &i, int &j) {
+    i = 0;
+    while ((i + 1) * (i + 2) / 2 <= t) ++i;
+    j = t - i * (i + 1) / 2;
+}
+
+__global__ void __launch_bounds__(512)
+k_gep_leaf(double2 *__restrict__ L, double2 *__restrict__ M, double2 *__restrict__ MH, int N,
+           int kb, int nb, int *__restrict__ info) {
+    __shared__ double2 T[LNT * 256];   // 144 KiB
+    __shared__ double2 Ti[256];        // inverse of the current diagonal tile
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+
+    // stage: element (i, k), k <= i, of the padded block
+    for (int e = tid; e < LB * LB; e += 512) {
+        const int i = e / LB, k = e % LB;
+        if (k <= i) {
+            double2 v = double2{i == k ? 1.0 : 0.0, 0.0};
+            if (i < nb) v = L[(long long)(kb + i) * N + kb + k];
+            ltile(T, i >> 4, k >> 4)[lsw(i & 15, k & 15)] = v;
+        }
     }
     __syncthreads();
-    for (int r = ty; r < 32; r += 8) {
-        const int gr = bx * 32 + r, gc = by * 32 + tx;   // destination (gr, gc) = conj(X[gc][gr])
-        if (gr < N && gc < N) {
-            double2 v = tile[tx][r];
-            v.y = -v.y;
-            Y[(long long)gr * N + gc] = v;
+
+    int inf = 0;
+    for (int P = 0; P < LT; ++P) {
+        if (w == 0) {
+            double2 *D = ltile(T, P, P);
+            double2 a[16], x[16];
+            const int r = lane & 15;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) a[k] = D[lsw(r, k)];
+            const int f = chol16(a, lane);
+            if (f != 0 && inf == 0 && 16 * P + f <= nb) inf = 16 * P + f;
+            inv16(a, x, lane);
+            if (lane < 16) {
+#pragma unroll
+                for (int k = 0; k < 16; ++k) D[lsw(lane, k)] = a[k];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) Ti[lsw(i, lane)] = x[i];
+            }
+        }
+        __syncthreads();
+        // panel: L_IP = C_IP inv(L_PP)^H
+        for (int I = P + 1 + w; I < LT; I += 8) {
+            double2 *C = ltile(T, I, P);
+            Cacc c;
+            acc_zero(c);
+            mma_abh(c, C, Ti, lane);
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                C[lsw(4 * v + (lane >> 4), lane & 15)] = double2{c.re[v], c.im[v]};
+        }
+        __syncthreads();
+        // trailing lower triangle: C_IJ -= L_IP L_JP^H
+        const int n = LT - 1 - P;
+        for (int t = w; t < n * (n + 1) / 2; t += 8) {
+            int ti, tj;
+            tri_decode(t, ti, tj);
+            const int I = P + 1 + ti, J = P + 1 + tj;
+            Cacc c;
+            acc_zero(c);
+            mma_abh(c, ltile(T, I, P), ltile(T, J, P), lane);
+            double2 *C = ltile(T, I, J);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                double2 &o = C[lsw(4 * v + (lane >> 4), lane & 15)];
+                o.x -= c.re[v];
+                o.y -= c.im[v];
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0 && inf != 0 && *info == 0) *info = kb + inf;
+    for (int e = tid; e < LB * LB; e += 512) {
+        const int i = e / LB, k = e % LB;
+        if (k <= i && i < nb)
+            L[(long long)(kb + i) * N + kb + k] = ltile(T, i >> 4, k >> 4)[lsw(i & 15, k & 15)];
+    }
+
+    // inverse: diagonal tiles, one per wave
+    {
+        double2 *D = ltile(T, w, w);
+        double2 a[16], x[16];
+        const int r = lane & 15;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) a[k] = D[lsw(r, k)];
+        inv16(a, x, lane);
+        if (lane < 16) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) D[lsw(i, lane)] = i >= lane ? x[i] : double2{0.0, 0.0};
+        }
+    }
+    __syncthreads();
+    // block rows: X_IJ = -X_II sum_{J<=K<I} L_IK X_KJ (wave w: J = w)
+    for (int I = 1; I < LT; ++I) {
+        Cacc c;
+        acc_zero(c);
+        if (w < I)
+            for (int K = w; K < I; ++K) mma_ab(c, ltile(T, I, K), ltile(T, K, w), lane);
+        __syncthreads();   // row I of L fully read before it is overwritten
+        if (w < I) {
+            const double2 *X = ltile(T, I, I);
+            Cacc o;
+            acc_zero(o);
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {   // B fragment rows 4 s4 .. = accumulator element s4
+                const double2 x = X[lsw(lane & 15, 4 * s4 + (lane >> 4))];
+                const double br = c.re[s4], bi = c.im[s4];
+                o.re = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x, br, o.re, 0, 0, 0);
+                o.re = __builtin_amdgcn_mfma_f64_16x16x4f64(x.y, -bi, o.re, 0, 0, 0);
+                o.im = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x, bi, o.im, 0, 0, 0);
+                o.im = __builtin_amdgcn_mfma_f64_16x16x4f64(x.y, br, o.im, 0, 0, 0);
+            }
+            double2 *C = ltile(T, I, w);
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                C[lsw(4 * v + (lane >> 4), lane & 15)] = double2{-o.re[v], -o.im[v]};
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < LB * LB; e += 512) {
+        const int i = e / LB, k = e % LB;
+        if (i < nb && k < nb) {
+            if (k <= i) M[(long long)(kb + i) * N + kb + k] = ltile(T, i >> 4, k >> 4)[lsw(i & 15, k & 15)];
+            else {   // MH[i][k] = conj(X[k][i]), k > i
+                const double2 v = ltile(T, k >> 4, i >> 4)[lsw(k & 15, i & 15)];
+                MH[(long long)(kb + i) * N + kb + k] = double2{v.x, -v.y};
+            }
+            if (k == i) {
+                const double2 v = ltile(T, i >> 4, i >> 4)[lsw(i & 15, i & 15)];
+                MH[(long long)(kb + i) * N + kb + k] = double2{v.x, -v.y};
+            }
         }
     }
 }
 
-hipError_t forward_substitution(double2 *L, double2 *LH, double2 *X, int N, hipStream_t st) {
-    using Cfg = GepCfg;
-    for (int kb = 0; kb < N; kb += GNB) {
-        const int nb = N - kb < GNB ? N - kb : GNB;
-        hipLaunchKernelGGL(k_gep_trsm, dim3((N + GNB - 1) / GNB), dim3(GT), 0, st, L, LH, X, N, kb,
-                           nb, 1);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+// L := lower(S) (upper triangle zero), M := 0, MH := 0
+__global__ void __launch_bounds__(256)
+k_gep_init(const double2 *__restrict__ S, double2 *__restrict__ L, double2 *__restrict__ M,
+           double2 *__restrict__ MH, int N) {
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (long long)N * N) return;
+    const int i = (int)(e / N), j = (int)(e % N);
+    L[e] = j <= i ? S[e] : double2{0.0, 0.0};
+    M[e] = double2{0.0, 0.0};
+    MH[e] = double2{0.0, 0.0};
+}
+
+__global__ void k_gep_info_clear(int *info) { *info = 0; }
+
+// D[j][i] = conj(X[i][j]) for i in [i0, i1), j in [j0, j1), through 32 x 32
+// LDS tiles (blockIdx.y: source tile row, blockIdx.x: source tile column)
+__global__ void __launch_bounds__(256)
+k_gep_conj_t(const double2 *__restrict__ X, double2 *__restrict__ D, int N, int i0, int i1, int j0,
+             int j1) {
+    __shared__ double2 tile[32][33];
+    const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+    const int si = i0 + blockIdx.y * 32, sj = j0 + blockIdx.x * 32;
+    for (int r = ty; r < 32; r += 8) {
+        const int gr = si + r, gc = sj + tx;
+        if (gr < i1 && gc < j1) tile[r][tx] = X[(long long)gr * N + gc];
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int dr = sj + r, dc = si + tx;   // D[dr][dc] = conj(X[dc][dr])
+        if (dr < j1 && dc < i1) {
+            double2 v = tile[tx][r];
+            v.y = -v.y;
+            D[(long long)dr * N + dc] = v;
+        }
+    }
+}
+
+struct Gep {
+    double2 *L, *LH, *M, *MH, *W;
+    int N;
+    int *info;
+    hipStream_t st;
+};
+
+hipError_t mm(const Gep &g, const double2 *P, const double2 *Q, double2 *C, int i0, int i1,
+              int j0, int j1, int k0, int k1, int flags, int op) {
+    using Cfg = MmCfg;
+    if (i1 <= i0 || j1 <= j0) return hipSuccess;
+    MmArgs a;
+    a.P = P;
+    a.Q = Q;
+    a.C = C;
+    a.N = g.N;
+    a.i0 = i0;
+    a.i1 = i1;
+    a.j0 = j0;
+    a.j1 = j1;
+    a.k0 = k0;
+    a.k1 = k1;
+    a.flags = flags;
+    a.op = op;
+    a.ntr = (i1 - i0 + Cfg::BM - 1) / Cfg::BM;
+    a.ntc = (j1 - j0 + Cfg::BN - 1) / Cfg::BN;
+    long long nblk;
+    if (flags & MM_LOWER) {
+        if (i0 != j0 || i1 != j1) return hipErrorInvalidValue;
+        nblk = (long long)a.ntr * (a.ntr + 1) / 2;
+    } else {
+        nblk = (long long)a.ntr * a.ntc;
+    }
+    hipLaunchKernelGGL(k_gep_mm, dim3((unsigned)nblk), dim3(Cfg::NT), 0, g.st, a);
+    return hipGetLastError();
+}
+
+hipError_t conj_t(const Gep &g, const double2 *X, double2 *D, int i0, int i1, int j0, int j1) {
+    if (i1 <= i0 || j1 <= j0) return hipSuccess;
+    hipLaunchKernelGGL(k_gep_conj_t, dim3((j1 - j0 + 31) / 32, (i1 - i0 + 31) / 32), dim3(256), 0,
+                       g.st, X, D, g.N, i0, i1, j0, j1);
+    return hipGetLastError();
+}
+
+#define GEP_TRY(x)                              \
+    do {                                        \
+        hipError_t e_ = (x);                    \
+        if (e_ != hipSuccess) return e_;        \
+    } while (0)
+
+// Cholesky, right-looking over panels of LB columns: factor and invert the
+// diagonal block, then the panel L21 = S21 L11^{-H} (as LH21 = M11 S21^H) and
+// the update of the trailing lower triangle S22 -= L21 L21^H.
+hipError_t factor(const Gep &g) {
+    const int N = g.N;
+    for (int kb = 0; kb < N; kb += LB) {
+        const int nb = N - kb < LB ? N - kb : LB;
         const int t0 = kb + nb;
-        if (t0 >= N) continue;
-        const int ntr = (N - t0 + Cfg::BM - 1) / Cfg::BM, ntc = (N + Cfg::BN - 1) / Cfg::BN;
-        hipLaunchKernelGGL(k_gep_update, dim3(ntr * ntc), dim3(Cfg::NT), 0, st, LH, X, X, N, kb, nb,
-                           0, ntc);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_gep_leaf, dim3(1), dim3(512), 0, g.st, g.L, g.M, g.MH, N, kb, nb,
+                           g.info);
+        GEP_TRY(hipGetLastError());
+        if (t0 >= N) break;
+        GEP_TRY(conj_t(g, g.L, g.W, t0, N, kb, t0));                              // W = S21^H
+        GEP_TRY(mm(g, g.MH, g.W, g.LH, kb, t0, t0, N, kb, t0, MM_PU, OP_STORE));   // LH21 = M11 S21^H
+        GEP_TRY(conj_t(g, g.LH, g.L, kb, t0, t0, N));                             // L21
+        GEP_TRY(mm(g, g.LH, g.LH, g.L, t0, N, t0, N, kb, t0, MM_LOWER, OP_SUB));  // S22 -= L21 L21^H
     }
     return hipSuccess;
 }
 
+// Inverse of the factor on [a, b), recursive over the same LB blocks the
+// factorization used (their inverses are in place): M21 = -M22 (L21 M11),
+// MH12 = M21^H.
+hipError_t invert(const Gep &g, int a, int b) {
+    const int n = b - a;
+    if (n <= LB) return hipSuccess;
+    const int h = (n / 2 + LB - 1) / LB * LB;   // multiple of LB, < n
+    const int m = a + h;
+    GEP_TRY(invert(g, a, m));
+    GEP_TRY(invert(g, m, b));
+    GEP_TRY(mm(g, g.LH, g.M, g.W, m, b, a, m, a, m, MM_QL, OP_STORE));   // W21 = L21 M11
+    GEP_TRY(mm(g, g.MH, g.W, g.M, m, b, a, m, m, b, MM_PU, OP_NEG));     // M21 = -M22 W21
+    return conj_t(g, g.M, g.MH, m, b, a, m);                             // MH12 = M21^H
+}
+
+size_t padded(size_t bytes) { return (bytes + 255) / 256 * 256; }
+
 }  // namespace
 
 size_t gep_workspace_bytes(int N) {
-    const size_t m = 16 * (size_t)N * (size_t)N;
-    return 2 * ((m + 255) / 256 * 256) + 256;   // LH, X, info slot
+    return 4 * padded(16 * (size_t)N * (size_t)N) + 256;   // LH, M, MH, W, info slot
 }
 
 hipError_t launch_gep(const double2 *H, const double2 *S, int N, double2 *L, double2 *Ht,
                       int *info, char *ws, hipStream_t st) {
-    using Cfg = GepCfg;
-    const size_t m = (16 * (size_t)N * (size_t)N + 255) / 256 * 256;
-    double2 *LH = reinterpret_cast<double2 *>(ws);
-    double2 *X = reinterpret_cast<double2 *>(ws + m);
-    if (!info) info = reinterpret_cast<int *>(ws + 2 * m);
+    const size_t m = padded(16 * (size_t)N * (size_t)N);
+    Gep g;
+    g.L = L;
+    g.LH = reinterpret_cast<double2 *>(ws);
+    g.M = reinterpret_cast<double2 *>(ws + m);
+    g.MH = reinterpret_cast<double2 *>(ws + 2 * m);
+    g.W = reinterpret_cast<double2 *>(ws + 3 * m);
+    g.N = N;
+    g.info = info ? info : reinterpret_cast<int *>(ws + 4 * m);
+    g.st = st;
     const long long nn = (long long)N * N;
-    hipLaunchKernelGGL(k_gep_init, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, H, S, L,
-                       X, N);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_gep_info_clear, dim3(1), dim3(1), 0, st, info);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    for (int kb = 0; kb < N; kb += GNB) {
-        const int nb = N - kb < GNB ? N - kb : GNB;
-        hipLaunchKernelGGL(k_gep_chol_diag, dim3(1), dim3(GT), 0, st, L, N, kb, nb, info);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        const int t0 = kb + nb;
-        if (t0 >= N) continue;
-        hipLaunchKernelGGL(k_gep_trsm, dim3((N - t0 + GNB - 1) / GNB), dim3(GT), 0, st, L, LH, X,
-                           N, kb, nb, 0);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        const int nt = (N - t0 + Cfg::BM - 1) / Cfg::BM;
-        hipLaunchKernelGGL(k_gep_update, dim3(nt * (nt + 1) / 2), dim3(Cfg::NT), 0, st, LH, LH, L,
-                           N, kb, nb, 1, 0);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    if ((e = forward_substitution(L, LH, X, N, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_gep_conj_t, dim3((N + 31) / 32, (N + 31) / 32), dim3(256), 0, st, X, Ht,
-                       N);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = forward_substitution(L, LH, Ht, N, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gep_init, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, S, L, g.M,
+                       g.MH, N);
+    GEP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_gep_info_clear, dim3(1), dim3(1), 0, st, g.info);
+    GEP_TRY(hipGetLastError());
+    GEP_TRY(factor(g));
+    GEP_TRY(invert(g, 0, N));
+    GEP_TRY(mm(g, H, g.MH, g.W, 0, N, 0, N, 0, N, MM_QU, OP_STORE));            // V = H MH
+    GEP_TRY(mm(g, g.W, g.MH, Ht, 0, N, 0, N, 0, N, MM_QU | MM_LOWER, OP_STORE)); // Ht = V^H MH
     return launch_mirror1(Ht, N, st);
 }
 
