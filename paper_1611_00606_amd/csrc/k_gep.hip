@@ -27,6 +27,8 @@
 // lower triangle during the factorization), LH (panels L21^H), M = L^{-1}
 // and MH = L^{-H} (zero outside their triangles), W (S21^H, L21 M11, then
 // V), Ht (output).
+#include <vector>
+
 #include "hs_internal.h"
 #include "zmfma_direct.h"
 #include "zmfma_tile.h"
@@ -45,50 +47,65 @@ constexpr int MM_LOWER = 8;   // only C's lower triangle (square region)
 // epilogue
 constexpr int OP_STORE = 0, OP_NEG = 1, OP_SUB = 2;
 
+// One product, or several independent ones on the same three matrices
+// (the nodes of one level of the inverse's recursion) in one launch.
+struct MmJob {
+    int i0, i1, j0, j1;       // C rows (P columns), C columns (Q columns)
+    int k0, k1;               // contraction rows of P and Q
+    int ntr, ntc;             // tile rows / columns of the rectangle
+    int start;                // first block of this job
+};
+constexpr int MM_JOBS = 32;
+
 struct MmArgs {
     const double2 *P, *Q;
     double2 *C;
     int N;                    // leading dimension of P, Q, C
-    int i0, i1, j0, j1;       // C rows (P columns), C columns (Q columns)
-    int k0, k1;               // contraction rows of P and Q
-    int ntr, ntc;             // tile rows / columns of the rectangle
     int flags, op;
+    int njobs;
+    MmJob job[MM_JOBS];
 };
 
-// C[i][j] (op)= sum_k conj(P[k][i]) Q[k][j] over the rectangle, in absolute
-// indices; the triangular flags trim each tile's contraction range to the
-// rows where both operands can be nonzero.
+// C[i][j] (op)= sum_k conj(P[k][i]) Q[k][j] over each job's rectangle, in
+// absolute indices; the triangular flags trim each tile's contraction range
+// to the rows where both operands can be nonzero.
 __global__ void __launch_bounds__(MmCfg::NT) k_gep_mm(const MmArgs args) {
     using Cfg = MmCfg;
     __shared__ double2 lds[Cfg::LDS_ELEMS];
     const int flags = args.flags;
     const int N = args.N;
+    int jb = 0;
+#pragma unroll
+    for (int t = 1; t < MM_JOBS; ++t)
+        if (t < args.njobs && (int)blockIdx.x >= args.job[t].start) jb = t;
+    const int bid = blockIdx.x - args.job[jb].start;
+    const int ntr = args.job[jb].ntr, ntc = args.job[jb].ntc;
+    const int i0 = args.job[jb].i0, i1 = args.job[jb].i1;
+    const int j0 = args.job[jb].j0, j1 = args.job[jb].j1;
     // Tiles whose contraction is longest go first (the triangular flags
     // make it depend on the tile row or column).
     int ti, tj;
-    const int bid = blockIdx.x;
     if (flags & MM_LOWER) {   // reversed row-major lower triangle: tj <= ti
-        const int t = gridDim.x - 1 - bid;
+        const int t = ntr * (ntr + 1) / 2 - 1 - bid;
         int r = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
         while ((r + 1) * (r + 2) / 2 <= t) ++r;
         while (r * (r + 1) / 2 > t) --r;
         ti = r;
         tj = t - r * (r + 1) / 2;
     } else if (flags & MM_PU) {   // longest: last tile rows
-        ti = args.ntr - 1 - bid / args.ntc;
-        tj = bid % args.ntc;
+        ti = ntr - 1 - bid / ntc;
+        tj = bid % ntc;
     } else if (flags & MM_QU) {   // longest: last tile columns
-        tj = args.ntc - 1 - bid / args.ntr;
-        ti = bid % args.ntr;
+        tj = ntc - 1 - bid / ntr;
+        ti = bid % ntr;
     } else {                      // MM_QL: first tile columns
-        tj = bid / args.ntr;
-        ti = bid % args.ntr;
+        tj = bid / ntr;
+        ti = bid % ntr;
     }
-    const int m0 = args.i0 + ti * Cfg::BM;
-    const int n0 = args.j0 + tj * Cfg::BN;
-    const int i1 = args.i1, j1 = args.j1;
+    const int m0 = i0 + ti * Cfg::BM;
+    const int n0 = j0 + tj * Cfg::BN;
     if (m0 >= i1 || n0 >= j1) return;
-    int klo = args.k0, khi = args.k1;
+    int klo = args.job[jb].k0, khi = args.job[jb].k1;
     if (flags & MM_PU) khi = min(khi, m0 + Cfg::BM);
     if (flags & MM_QU) khi = min(khi, n0 + Cfg::BN);
     if (flags & MM_QL) klo = max(klo, n0);
@@ -425,34 +442,59 @@ struct Gep {
     hipStream_t st;
 };
 
+#define GEP_TRY(x)                              \
+    do {                                        \
+        hipError_t e_ = (x);                    \
+        if (e_ != hipSuccess) return e_;        \
+    } while (0)
+
+struct Rect {
+    int i0, i1, j0, j1, k0, k1;
+};
+
+// Products over the rectangles r[0 .. n), up to MM_JOBS per launch.
+hipError_t mm_batch(const Gep &g, const double2 *P, const double2 *Q, double2 *C, const Rect *r,
+                    int n, int flags, int op) {
+    using Cfg = MmCfg;
+    for (int b = 0; b < n; b += MM_JOBS) {
+        MmArgs a = {};
+        a.P = P;
+        a.Q = Q;
+        a.C = C;
+        a.N = g.N;
+        a.flags = flags;
+        a.op = op;
+        long long nblk = 0;
+        for (int t = b; t < n && t < b + MM_JOBS; ++t) {
+            if (r[t].i1 <= r[t].i0 || r[t].j1 <= r[t].j0) continue;
+            MmJob &j = a.job[a.njobs++];
+            j.i0 = r[t].i0;
+            j.i1 = r[t].i1;
+            j.j0 = r[t].j0;
+            j.j1 = r[t].j1;
+            j.k0 = r[t].k0;
+            j.k1 = r[t].k1;
+            j.ntr = (j.i1 - j.i0 + Cfg::BM - 1) / Cfg::BM;
+            j.ntc = (j.j1 - j.j0 + Cfg::BN - 1) / Cfg::BN;
+            j.start = (int)nblk;
+            if (flags & MM_LOWER) {
+                if (j.i0 != j.j0 || j.i1 != j.j1) return hipErrorInvalidValue;
+                nblk += (long long)j.ntr * (j.ntr + 1) / 2;
+            } else {
+                nblk += (long long)j.ntr * j.ntc;
+            }
+        }
+        if (a.njobs == 0) continue;
+        hipLaunchKernelGGL(k_gep_mm, dim3((unsigned)nblk), dim3(Cfg::NT), 0, g.st, a);
+        GEP_TRY(hipGetLastError());
+    }
+    return hipSuccess;
+}
+
 hipError_t mm(const Gep &g, const double2 *P, const double2 *Q, double2 *C, int i0, int i1,
               int j0, int j1, int k0, int k1, int flags, int op) {
-    using Cfg = MmCfg;
-    if (i1 <= i0 || j1 <= j0) return hipSuccess;
-    MmArgs a;
-    a.P = P;
-    a.Q = Q;
-    a.C = C;
-    a.N = g.N;
-    a.i0 = i0;
-    a.i1 = i1;
-    a.j0 = j0;
-    a.j1 = j1;
-    a.k0 = k0;
-    a.k1 = k1;
-    a.flags = flags;
-    a.op = op;
-    a.ntr = (i1 - i0 + Cfg::BM - 1) / Cfg::BM;
-    a.ntc = (j1 - j0 + Cfg::BN - 1) / Cfg::BN;
-    long long nblk;
-    if (flags & MM_LOWER) {
-        if (i0 != j0 || i1 != j1) return hipErrorInvalidValue;
-        nblk = (long long)a.ntr * (a.ntr + 1) / 2;
-    } else {
-        nblk = (long long)a.ntr * a.ntc;
-    }
-    hipLaunchKernelGGL(k_gep_mm, dim3((unsigned)nblk), dim3(Cfg::NT), 0, g.st, a);
-    return hipGetLastError();
+    const Rect r = {i0, i1, j0, j1, k0, k1};
+    return mm_batch(g, P, Q, C, &r, 1, flags, op);
 }
 
 hipError_t conj_t(const Gep &g, const double2 *X, double2 *D, int i0, int i1, int j0, int j1) {
@@ -461,12 +503,6 @@ hipError_t conj_t(const Gep &g, const double2 *X, double2 *D, int i0, int i1, in
                        g.st, X, D, g.N, i0, i1, j0, j1);
     return hipGetLastError();
 }
-
-#define GEP_TRY(x)                              \
-    do {                                        \
-        hipError_t e_ = (x);                    \
-        if (e_ != hipSuccess) return e_;        \
-    } while (0)
 
 // Cholesky, right-looking over panels of LB columns: factor and invert the
 // diagonal block, then the panel L21 = S21 L11^{-H} (as LH21 = M11 S21^H) and
@@ -488,19 +524,38 @@ hipError_t factor(const Gep &g) {
     return hipSuccess;
 }
 
-// Inverse of the factor on [a, b), recursive over the same LB blocks the
-// factorization used (their inverses are in place): M21 = -M22 (L21 M11),
-// MH12 = M21^H.
-hipError_t invert(const Gep &g, int a, int b) {
+// Inverse of the factor, M = L^{-1}, over the recursion tree of [0, N) split
+// at multiples of LB (the leaves' inverses are in place): per node [a, b)
+// split at m, M21 = -M22 (L21 M11) and MH12 = M21^H. The nodes of one depth
+// are independent; each depth, deepest first, runs as two batched launches.
+struct Node {
+    int a, m, b;
+};
+
+void tree(int a, int b, int depth, std::vector<std::vector<Node>> &lv) {
     const int n = b - a;
-    if (n <= LB) return hipSuccess;
-    const int h = (n / 2 + LB - 1) / LB * LB;   // multiple of LB, < n
-    const int m = a + h;
-    GEP_TRY(invert(g, a, m));
-    GEP_TRY(invert(g, m, b));
-    GEP_TRY(mm(g, g.LH, g.M, g.W, m, b, a, m, a, m, MM_QL, OP_STORE));   // W21 = L21 M11
-    GEP_TRY(mm(g, g.MH, g.W, g.M, m, b, a, m, m, b, MM_PU, OP_NEG));     // M21 = -M22 W21
-    return conj_t(g, g.M, g.MH, m, b, a, m);                             // MH12 = M21^H
+    if (n <= LB) return;
+    const int m = a + (n / 2 + LB - 1) / LB * LB;   // multiple of LB, < b
+    if ((int)lv.size() <= depth) lv.resize(depth + 1);
+    lv[depth].push_back(Node{a, m, b});
+    tree(a, m, depth + 1, lv);
+    tree(m, b, depth + 1, lv);
+}
+
+hipError_t invert(const Gep &g) {
+    std::vector<std::vector<Node>> lv;
+    tree(0, g.N, 0, lv);
+    std::vector<Rect> r;
+    for (int d = (int)lv.size() - 1; d >= 0; --d) {
+        r.clear();
+        for (const Node &n : lv[d]) r.push_back(Rect{n.m, n.b, n.a, n.m, n.a, n.m});
+        GEP_TRY(mm_batch(g, g.LH, g.M, g.W, r.data(), (int)r.size(), MM_QL, OP_STORE));  // W21 = L21 M11
+        r.clear();
+        for (const Node &n : lv[d]) r.push_back(Rect{n.m, n.b, n.a, n.m, n.m, n.b});
+        GEP_TRY(mm_batch(g, g.MH, g.W, g.M, r.data(), (int)r.size(), MM_PU, OP_NEG));    // M21 = -M22 W21
+        for (const Node &n : lv[d]) GEP_TRY(conj_t(g, g.M, g.MH, n.m, n.b, n.a, n.m));    // MH12
+    }
+    return hipSuccess;
 }
 
 size_t padded(size_t bytes) { return (bytes + 255) / 256 * 256; }
@@ -530,7 +585,7 @@ hipError_t launch_gep(const double2 *H, const double2 *S, int N, double2 *L, dou
     hipLaunchKernelGGL(k_gep_info_clear, dim3(1), dim3(1), 0, st, g.info);
     GEP_TRY(hipGetLastError());
     GEP_TRY(factor(g));
-    GEP_TRY(invert(g, 0, N));
+    GEP_TRY(invert(g));
     GEP_TRY(mm(g, H, g.MH, g.W, 0, N, 0, N, 0, N, MM_QU, OP_STORE));            // V = H MH
     GEP_TRY(mm(g, g.W, g.MH, Ht, 0, N, 0, N, 0, N, MM_QU | MM_LOWER, OP_STORE)); // Ht = V^H MH
     return launch_mirror1(Ht, N, st);
