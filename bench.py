@@ -107,16 +107,20 @@ class HipEvents:
             self.rt.hipEventDestroy(ctypes.c_void_p(e))
 
 
+def _blas_threads() -> int:
+    try:
+        from threadpoolctl import threadpool_info
+        return int(max([i.get("num_threads", 1) for i in threadpool_info()
+                        if i.get("user_api") == "blas"] or [1]))
+    except Exception:
+        return len(os.sched_getaffinity(0))
+
+
 def cpu_baseline(p, seconds: float):
     """Time the CPU oracle on the first atoms of the workload (full N_G)."""
     import oracle
     from paper_1611_00606_amd.flops import algorithmic_flops
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()
-                       if i.get("user_api") == "blas"] or [1])
-    except Exception:
-        threads = len(os.sched_getaffinity(0))
+    threads = _blas_threads()
 
     def run(n_atoms):
         k = int(p.nl[:n_atoms].sum())
@@ -407,6 +411,68 @@ def serving_bench(seed: int, n_slots: int = 4, arena_gb: float = 24.0, n_sets: i
     return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in out.items()}
 
 
+def gep_bench(run, steps: int, hip):
+    """Reduction of the generalized eigenproblem (S = L L^H, Ht = L^-1 H L^-H)
+    applied to the H and S this build produced, timed with HIP events on the
+    launch stream."""
+    import torch
+    from paper_1611_00606_amd import hs_gep_reduce, hs_gep_workspace_bytes
+    N = int(run.H.shape[0])
+    dev = run.H.device
+    L = torch.empty_like(run.H)
+    Ht = torch.empty_like(run.H)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws = torch.empty(hs_gep_workspace_bytes(N), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    hs_gep_reduce(run.H, run.S, L, Ht, info=info, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
+    rt = hip.rt
+    rt.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    ms = []
+    for _ in range(steps):
+        e0, e1 = hip.create(2)
+        assert rt.hipEventRecord(ctypes.c_void_p(e0), ctypes.c_void_p(stream.cuda_stream)) == 0
+        hs_gep_reduce(run.H, run.S, L, Ht, info=info, workspace=ws, stream=stream)
+        assert rt.hipEventRecord(ctypes.c_void_p(e1), ctypes.c_void_p(stream.cuda_stream)) == 0
+        torch.cuda.synchronize()
+        ms.append(hip.elapsed_ms(e0, e1))
+        hip.destroy([e0, e1])
+    res = float(torch.linalg.matrix_norm(L @ L.conj().T - run.S) / torch.linalg.matrix_norm(run.S))
+    med = float(np.median(ms))
+    f_def = 28.0 / 3.0 * N ** 3    # Cholesky + two triangular solves with N columns
+    f_exec = 8.0 * N ** 3          # factor, inverse and the two triangular products executed
+    out = {
+        "N": N, "info": int(info.item()),
+        "ms_median": round(med, 3), "ms_min": round(float(min(ms)), 3),
+        "tflops_by_definition": round(f_def / (med * 1e-3) / 1e12, 2),
+        "tflops_executed": round(f_exec / (med * 1e-3) / 1e12, 2),
+        "pct_of_fp64_mfma_peak_executed": round(100 * f_exec / (med * 1e-3) / 1e12
+                                                / FP64_MFMA_PEAK_TFLOPS, 1),
+        "residual_S_LLH": res,
+        "flop_counts": "by_definition 28/3 N^3 (Cholesky 4/3 N^3 + two solves 4 N^3 each); "
+                       "executed 8 N^3",
+    }
+    del L, Ht, ws
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline_gep(n_full: int, n: int = 2000):
+    """The oracle's reduction (column Cholesky + scipy triangular solves) on a
+    bounded sample, N = n, and that time scaled by (n_full / n)^3."""
+    import oracle as O
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    S = A @ A.conj().T + n * np.eye(n)
+    H = A + A.conj().T
+    t0 = time.perf_counter()
+    O.gep_reduce(H, S)
+    t = time.perf_counter() - t0
+    return {"kind": "oracle", "sample": f"random Hermitian pair, N = {n}",
+            "ms": round(1e3 * t, 1), "ms_scaled_to_full_N": round(1e3 * t * (n_full / n) ** 3, 1),
+            "cores": _blas_threads()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -427,6 +493,8 @@ def main():
                          "autotuned tile shapes, or separate preparation and product launches")
     ap.add_argument("--no-batching", action="store_true",
                     help="skip the batched per-atom stage measurement")
+    ap.add_argument("--no-gep", action="store_true",
+                    help="skip the generalized eigenproblem reduction of the built H and S")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run one plain device copy of MIB MiB (to scale HBM byte "
                          "counters against a kernel of known traffic) and exit")
@@ -544,6 +612,9 @@ def main():
         },
         "cpu_baseline": None,
     }
+    if not args.no_gep:
+        print("bench: generalized eigenproblem reduction", file=sys.stderr, flush=True)
+        out["gep"] = gep_bench(run, max(3, args.steps // 2), HipEvents())
     del run
     torch.cuda.empty_cache()
     out["hs_build_sync_wall_ms"] = sync_build_wall_ms(p)
@@ -558,6 +629,8 @@ def main():
         out["batching"] = batching_bench(args.seed, max(3, args.steps // 2), HipEvents())
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+        if "gep" in out:
+            out["gep"]["cpu_baseline"] = cpu_baseline_gep(out["gep"]["N"])
     if not args.no_serving:
         print("bench: serving stream", file=sys.stderr, flush=True)
         out["serving"] = serving_bench(args.seed)
