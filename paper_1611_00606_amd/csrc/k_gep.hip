@@ -27,6 +27,7 @@
 // lower triangle during the factorization), LH (panels L21^H), M = L^{-1}
 // and MH = L^{-H} (zero outside their triangles), W (S21^H, L21 M11, then
 // V), Ht (output).
+#include <mutex>
 #include <vector>
 
 #include "hs_internal.h"
@@ -44,6 +45,7 @@ constexpr int MM_PU = 1;      // P upper triangular: k <= row of C
 constexpr int MM_QL = 2;      // Q lower triangular: k >= column of C
 constexpr int MM_QU = 4;      // Q upper triangular: k <= column of C
 constexpr int MM_LOWER = 8;   // only C's lower triangle (square region)
+constexpr int MM_MASK = 16;   // only elements on or below the diagonal (any region)
 // epilogue
 constexpr int OP_STORE = 0, OP_NEG = 1, OP_SUB = 2;
 
@@ -85,13 +87,19 @@ __global__ void __launch_bounds__(MmCfg::NT) k_gep_mm(const MmArgs args) {
     // Tiles whose contraction is longest go first (the triangular flags
     // make it depend on the tile row or column).
     int ti, tj;
-    if (flags & MM_LOWER) {   // reversed row-major lower triangle: tj <= ti
-        const int t = ntr * (ntr + 1) / 2 - 1 - bid;
+    if (flags & MM_LOWER) {   // lower triangle, tj <= ti
+        const bool byc = flags & MM_QU;   // contraction grows with tj: last columns first
+        const int t = byc ? bid : ntr * (ntr + 1) / 2 - 1 - bid;
         int r = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
         while ((r + 1) * (r + 2) / 2 <= t) ++r;
         while (r * (r + 1) / 2 > t) --r;
-        ti = r;
-        tj = t - r * (r + 1) / 2;
+        if (byc) {   // column ntr-1-r, its r+1 tiles from the diagonal down
+            tj = ntr - 1 - r;
+            ti = tj + (t - r * (r + 1) / 2);
+        } else {     // reversed row-major
+            ti = r;
+            tj = t - r * (r + 1) / 2;
+        }
     } else if (flags & MM_PU) {   // longest: last tile rows
         ti = ntr - 1 - bid / ntc;
         tj = bid % ntc;
@@ -123,7 +131,7 @@ __global__ void __launch_bounds__(MmCfg::NT) k_gep_mm(const MmArgs args) {
     Acc<Cfg> acc;
     ztile_direct<Cfg>(t, m0, i1, n0, j1, acc, lds);
 
-    const bool lower = flags & MM_LOWER;
+    const bool lower = flags & (MM_LOWER | MM_MASK);
     const int op = args.op;
     double2 *C = args.C;
 #pragma unroll
@@ -504,24 +512,80 @@ hipError_t conj_t(const Gep &g, const double2 *X, double2 *D, int i0, int i1, in
     return hipGetLastError();
 }
 
+// Auxiliary stream per device for the lookahead below (default priority,
+// created once, kept for the life of the process).
+hipStream_t aux_stream() {
+    static std::mutex mu;
+    static hipStream_t cached[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!cached[dev]) {
+        hipStream_t s = nullptr;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+        cached[dev] = s;
+    }
+    return cached[dev];
+}
+
 // Cholesky, right-looking over panels of LB columns: factor and invert the
 // diagonal block, then the panel L21 = S21 L11^{-H} (as LH21 = M11 S21^H) and
 // the update of the trailing lower triangle S22 -= L21 L21^H.
+// Lookahead (from 4 panels on): the update is split into the next column
+// block, applied on the caller's stream, and the rest, applied on an
+// auxiliary stream, so that the next panel's leaf, transposes and panel
+// product overlap the bulk of the update. The next column block's update
+// waits for the previous bulk update (both write that block); the bulk
+// update waits for the panel it applies.
 hipError_t factor(const Gep &g) {
     const int N = g.N;
-    for (int kb = 0; kb < N; kb += LB) {
+    const int np = (N + LB - 1) / LB;
+    Gep ga = g;
+    hipEvent_t e_panel = nullptr, e_bulk = nullptr;
+    bool ahead = np >= 4;
+    if (ahead) {
+        ga.st = aux_stream();
+        ahead = ga.st != nullptr &&
+                hipEventCreateWithFlags(&e_panel, hipEventDisableTiming) == hipSuccess &&
+                hipEventCreateWithFlags(&e_bulk, hipEventDisableTiming) == hipSuccess;
+    }
+    bool bulk_pending = false;   // e_bulk recorded (no wait on an unrecorded event)
+    hipError_t err = hipSuccess;
+    for (int kb = 0; kb < N && err == hipSuccess; kb += LB) {
         const int nb = N - kb < LB ? N - kb : LB;
         const int t0 = kb + nb;
         hipLaunchKernelGGL(k_gep_leaf, dim3(1), dim3(512), 0, g.st, g.L, g.M, g.MH, N, kb, nb,
                            g.info);
-        GEP_TRY(hipGetLastError());
-        if (t0 >= N) break;
-        GEP_TRY(conj_t(g, g.L, g.W, t0, N, kb, t0));                              // W = S21^H
-        GEP_TRY(mm(g, g.MH, g.W, g.LH, kb, t0, t0, N, kb, t0, MM_PU, OP_STORE));   // LH21 = M11 S21^H
-        GEP_TRY(conj_t(g, g.LH, g.L, kb, t0, t0, N));                             // L21
-        GEP_TRY(mm(g, g.LH, g.LH, g.L, t0, N, t0, N, kb, t0, MM_LOWER, OP_SUB));  // S22 -= L21 L21^H
+        if ((err = hipGetLastError()) != hipSuccess || t0 >= N) break;
+        if ((err = conj_t(g, g.L, g.W, t0, N, kb, t0)) != hipSuccess) break;     // W = S21^H
+        if ((err = mm(g, g.MH, g.W, g.LH, kb, t0, t0, N, kb, t0, MM_PU, OP_STORE)) != hipSuccess)
+            break;                                                                // LH21 = M11 S21^H
+        if ((err = conj_t(g, g.LH, g.L, kb, t0, t0, N)) != hipSuccess) break;    // L21
+        if (!ahead) {
+            err = mm(g, g.LH, g.LH, g.L, t0, N, t0, N, kb, t0, MM_LOWER, OP_SUB); // S22 -= L21 L21^H
+            continue;
+        }
+        const int t1 = N - t0 < LB ? N : t0 + LB;
+        if ((err = hipEventRecord(e_panel, g.st)) != hipSuccess) break;
+        if (bulk_pending && (err = hipStreamWaitEvent(g.st, e_bulk, 0)) != hipSuccess) break;
+        if ((err = mm(g, g.LH, g.LH, g.L, t0, N, t0, t1, kb, t0, MM_MASK, OP_SUB)) != hipSuccess)
+            break;                                                                // next column block
+        if (t1 < N) {
+            if ((err = hipStreamWaitEvent(ga.st, e_panel, 0)) != hipSuccess) break;
+            if ((err = mm(ga, g.LH, g.LH, g.L, t1, N, t1, N, kb, t0, MM_LOWER, OP_SUB)) !=
+                hipSuccess)
+                break;                                                            // the rest
+            if ((err = hipEventRecord(e_bulk, ga.st)) != hipSuccess) break;
+            bulk_pending = true;
+        }
     }
-    return hipSuccess;
+    if (bulk_pending) {
+        const hipError_t e = hipStreamWaitEvent(g.st, e_bulk, 0);
+        if (err == hipSuccess) err = e;
+    }
+    if (e_panel) (void)hipEventDestroy(e_panel);
+    if (e_bulk) (void)hipEventDestroy(e_bulk);
+    return err;
 }
 
 // Inverse of the factor, M = L^{-1}, over the recursion tree of [0, N) split
