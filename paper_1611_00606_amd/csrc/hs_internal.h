@@ -55,6 +55,7 @@ void set_error(const std::string &msg);
 const std::string &last_error();
 int hip_fail(hipError_t e, const char *where);   // records the message, returns HS_ERR_HIP
 int check_device();                              // HS_OK on gfx950, else an error status
+int num_cus();                                   // compute units of the current device
 inline bool valid_mode(int mode) {   // HS_FP64, HS_SPLIT_F16, HS_SPLIT_I8
     return mode == HS_FP64 || mode == HS_SPLIT_F16 || mode == HS_SPLIT_I8;
 }

@@ -244,6 +244,9 @@ __global__ void __launch_bounds__(256) k_batch_check(const int *ctrl, int *info,
     for (int a = blockIdx.x * 256 + threadIdx.x; a < n_atoms; a += gridDim.x * 256) info[a] = -1;
 }
 
+}  // namespace
+
+// Compute units of the current device (cached per device).
 int num_cus() {
     static int cached[64] = {};
     int dev = 0;
@@ -257,8 +260,6 @@ int num_cus() {
     }
     return cached[dev];
 }
-
-}  // namespace
 
 int tile_shape(int id, int *bm, int *bn) {
     static const int shapes[HS_NUM_TILE_CONFIGS][2] = {

@@ -4,7 +4,8 @@
 //
 // The O(N^3) work runs as products on the complex FP64 MFMA tile engine with
 // direct global -> LDS loads (zmfma_direct.h):
-//   factor, right-looking over panels of LB = 128 columns:
+//   factor, right-looking over panels of LB = 128 columns (lookahead on a
+//   second stream):
 //     k_gep_leaf                        Cholesky of the diagonal block and the
 //                                       inverse M11 = L11^{-1} (one workgroup)
 //     LH21 = M11 S21^H                  (= L21^H, the panel)
@@ -23,10 +24,14 @@
 // eigensolvers; its error grows with cond(L) = cond(S)^{1/2} like that of
 // the substitutions.
 //
+// Once the factorization passes the top split of the inverse's recursion,
+// the leading block's inverse and the matching columns of V run on a third
+// stream beside it.
+//
 // Storage (all N x N row-major complex): L (output; working copy of S's
-// lower triangle during the factorization), LH (panels L21^H), M = L^{-1}
-// and MH = L^{-H} (zero outside their triangles), W (S21^H, L21 M11, then
-// V), Ht (output).
+// lower triangle during the factorization), LH (panels L21^H, then V),
+// M = L^{-1} and MH = L^{-H} (zero outside their triangles), W (S21^H,
+// L21 M11), Ht (output).
 #include <mutex>
 #include <vector>
 
@@ -65,22 +70,22 @@ struct MmArgs {
     int N;                    // leading dimension of P, Q, C
     int flags, op;
     int njobs;
+    int total;                // tiles over all jobs (blocks loop over them)
     MmJob job[MM_JOBS];
 };
 
 // C[i][j] (op)= sum_k conj(P[k][i]) Q[k][j] over each job's rectangle, in
 // absolute indices; the triangular flags trim each tile's contraction range
 // to the rows where both operands can be nonzero.
-__global__ void __launch_bounds__(MmCfg::NT) k_gep_mm(const MmArgs args) {
+__device__ __forceinline__ void mm_tile(const MmArgs &args, int tile, double2 *lds) {
     using Cfg = MmCfg;
-    __shared__ double2 lds[Cfg::LDS_ELEMS];
     const int flags = args.flags;
     const int N = args.N;
     int jb = 0;
 #pragma unroll
     for (int t = 1; t < MM_JOBS; ++t)
-        if (t < args.njobs && (int)blockIdx.x >= args.job[t].start) jb = t;
-    const int bid = blockIdx.x - args.job[jb].start;
+        if (t < args.njobs && tile >= args.job[t].start) jb = t;
+    const int bid = tile - args.job[jb].start;
     const int ntr = args.job[jb].ntr, ntc = args.job[jb].ntc;
     const int i0 = args.job[jb].i0, i1 = args.job[jb].i1;
     const int j0 = args.job[jb].j0, j1 = args.job[jb].j1;
@@ -158,6 +163,16 @@ __global__ void __launch_bounds__(MmCfg::NT) k_gep_mm(const MmArgs args) {
                 }
             }
         }
+}
+
+// Blocks loop over the tiles (a launch may have fewer blocks than tiles when
+// it runs beside latency-critical work).
+__global__ void __launch_bounds__(MmCfg::NT) k_gep_mm(const MmArgs args) {
+    __shared__ double2 lds[MmCfg::LDS_ELEMS];
+    for (int tile = blockIdx.x; tile < args.total; tile += gridDim.x) {
+        mm_tile(args, tile, lds);
+        __syncthreads();   // LDS is reused by the next tile
+    }
 }
 
 // Leaf: Cholesky of the diagonal block [kb, kb + nb) (nb <= LB = 128) of the
@@ -448,6 +463,7 @@ struct Gep {
     int N;
     int *info;
     hipStream_t st;
+    int cap;   // most blocks per product launch (0: one per tile)
 };
 
 #define GEP_TRY(x)                              \
@@ -493,7 +509,9 @@ hipError_t mm_batch(const Gep &g, const double2 *P, const double2 *Q, double2 *C
             }
         }
         if (a.njobs == 0) continue;
-        hipLaunchKernelGGL(k_gep_mm, dim3((unsigned)nblk), dim3(Cfg::NT), 0, g.st, a);
+        a.total = (int)nblk;
+        const long long grid = g.cap > 0 && nblk > g.cap ? g.cap : nblk;
+        hipLaunchKernelGGL(k_gep_mm, dim3((unsigned)grid), dim3(Cfg::NT), 0, g.st, a);
         GEP_TRY(hipGetLastError());
     }
     return hipSuccess;
@@ -512,20 +530,21 @@ hipError_t conj_t(const Gep &g, const double2 *X, double2 *D, int i0, int i1, in
     return hipGetLastError();
 }
 
-// Auxiliary stream per device for the lookahead below (default priority,
-// created once, kept for the life of the process).
-hipStream_t aux_stream() {
+// Auxiliary streams per device (index 0: the factorization's lookahead,
+// 1: work moved off the critical path); default priority, created once and
+// kept for the life of the process.
+hipStream_t aux_stream(int which) {
     static std::mutex mu;
-    static hipStream_t cached[64] = {};
+    static hipStream_t cached[64][2] = {};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
     std::lock_guard<std::mutex> lk(mu);
-    if (!cached[dev]) {
+    if (!cached[dev][which]) {
         hipStream_t s = nullptr;
         if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
-        cached[dev] = s;
+        cached[dev][which] = s;
     }
-    return cached[dev];
+    return cached[dev][which];
 }
 
 // Cholesky, right-looking over panels of LB columns: factor and invert the
@@ -537,14 +556,15 @@ hipStream_t aux_stream() {
 // product overlap the bulk of the update. The next column block's update
 // waits for the previous bulk update (both write that block); the bulk
 // update waits for the panel it applies.
-hipError_t factor(const Gep &g) {
+template <class Hook>
+hipError_t factor(const Gep &g, Hook after_leaf) {
     const int N = g.N;
     const int np = (N + LB - 1) / LB;
     Gep ga = g;
     hipEvent_t e_panel = nullptr, e_bulk = nullptr;
     bool ahead = np >= 4;
     if (ahead) {
-        ga.st = aux_stream();
+        ga.st = aux_stream(0);
         ahead = ga.st != nullptr &&
                 hipEventCreateWithFlags(&e_panel, hipEventDisableTiming) == hipSuccess &&
                 hipEventCreateWithFlags(&e_bulk, hipEventDisableTiming) == hipSuccess;
@@ -556,7 +576,8 @@ hipError_t factor(const Gep &g) {
         const int t0 = kb + nb;
         hipLaunchKernelGGL(k_gep_leaf, dim3(1), dim3(512), 0, g.st, g.L, g.M, g.MH, N, kb, nb,
                            g.info);
-        if ((err = hipGetLastError()) != hipSuccess || t0 >= N) break;
+        if ((err = hipGetLastError()) != hipSuccess) break;
+        if ((err = after_leaf(t0)) != hipSuccess || t0 >= N) break;
         if ((err = conj_t(g, g.L, g.W, t0, N, kb, t0)) != hipSuccess) break;     // W = S21^H
         if ((err = mm(g, g.MH, g.W, g.LH, kb, t0, t0, N, kb, t0, MM_PU, OP_STORE)) != hipSuccess)
             break;                                                                // LH21 = M11 S21^H
@@ -606,18 +627,22 @@ void tree(int a, int b, int depth, std::vector<std::vector<Node>> &lv) {
     tree(m, b, depth + 1, lv);
 }
 
-hipError_t invert(const Gep &g) {
-    std::vector<std::vector<Node>> lv;
-    tree(0, g.N, 0, lv);
+template <class Keep>
+hipError_t invert(const Gep &g, const std::vector<std::vector<Node>> &lv, Keep keep) {
     std::vector<Rect> r;
+    std::vector<Node> nodes;
     for (int d = (int)lv.size() - 1; d >= 0; --d) {
+        nodes.clear();
+        for (const Node &n : lv[d])
+            if (keep(n)) nodes.push_back(n);
+        if (nodes.empty()) continue;
         r.clear();
-        for (const Node &n : lv[d]) r.push_back(Rect{n.m, n.b, n.a, n.m, n.a, n.m});
+        for (const Node &n : nodes) r.push_back(Rect{n.m, n.b, n.a, n.m, n.a, n.m});
         GEP_TRY(mm_batch(g, g.LH, g.M, g.W, r.data(), (int)r.size(), MM_QL, OP_STORE));  // W21 = L21 M11
         r.clear();
-        for (const Node &n : lv[d]) r.push_back(Rect{n.m, n.b, n.a, n.m, n.m, n.b});
+        for (const Node &n : nodes) r.push_back(Rect{n.m, n.b, n.a, n.m, n.m, n.b});
         GEP_TRY(mm_batch(g, g.MH, g.W, g.M, r.data(), (int)r.size(), MM_PU, OP_NEG));    // M21 = -M22 W21
-        for (const Node &n : lv[d]) GEP_TRY(conj_t(g, g.M, g.MH, n.m, n.b, n.a, n.m));    // MH12
+        for (const Node &n : nodes) GEP_TRY(conj_t(g, g.M, g.MH, n.m, n.b, n.a, n.m));    // MH12
     }
     return hipSuccess;
 }
@@ -648,10 +673,59 @@ hipError_t launch_gep(const double2 *H, const double2 *S, int N, double2 *L, dou
     GEP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_gep_info_clear, dim3(1), dim3(1), 0, st, g.info);
     GEP_TRY(hipGetLastError());
-    GEP_TRY(factor(g));
-    GEP_TRY(invert(g));
-    GEP_TRY(mm(g, H, g.MH, g.W, 0, N, 0, N, 0, N, MM_QU, OP_STORE));            // V = H MH
-    GEP_TRY(mm(g, g.W, g.MH, Ht, 0, N, 0, N, 0, N, MM_QU | MM_LOWER, OP_STORE)); // Ht = V^H MH
+    g.cap = 0;
+    std::vector<std::vector<Node>> lv;
+    tree(0, N, 0, lv);
+    const auto all = [](const Node &) { return true; };
+    const int np = (N + LB - 1) / LB;
+    hipStream_t sb = np >= 8 ? aux_stream(1) : nullptr;
+    if (!sb) {
+        GEP_TRY(factor(g, [](int) { return hipSuccess; }));
+        GEP_TRY(invert(g, lv, all));
+        GEP_TRY(mm(g, H, g.MH, g.LH, 0, N, 0, N, 0, N, MM_QU, OP_STORE));              // V = H MH
+        GEP_TRY(mm(g, g.LH, g.MH, Ht, 0, N, 0, N, 0, N, MM_QU | MM_LOWER, OP_STORE));  // Ht = V^H MH
+        return launch_mirror1(Ht, N, st);
+    }
+    // Once the factorization has passed the top split m, the inverse of the
+    // leading block [0, m) and the columns [0, m) of V = H MH depend on nothing
+    // still to come: they run on a second stream, with at most 3/4 of the
+    // compute units, beside the rest of the factorization. V is kept in LH,
+    // whose columns < m the factorization no longer touches by then.
+    const Node top = lv[0][0];
+    const int mt = top.m;
+    Gep gb = g;
+    gb.st = sb;
+    gb.cap = num_cus() * 3 / 4;
+    hipEvent_t e_split = nullptr, e_inv = nullptr, e_v = nullptr;
+    hipError_t err = hipEventCreateWithFlags(&e_split, hipEventDisableTiming);
+    if (err == hipSuccess) err = hipEventCreateWithFlags(&e_inv, hipEventDisableTiming);
+    if (err == hipSuccess) err = hipEventCreateWithFlags(&e_v, hipEventDisableTiming);
+    bool forked = false;
+    const auto left = [mt](const Node &n) { return n.b <= mt; };
+    if (err == hipSuccess)
+        err = factor(g, [&](int t0) -> hipError_t {
+            if (t0 != mt) return hipSuccess;
+            GEP_TRY(hipEventRecord(e_split, st));
+            GEP_TRY(hipStreamWaitEvent(sb, e_split, 0));
+            forked = true;
+            GEP_TRY(invert(gb, lv, left));
+            GEP_TRY(hipEventRecord(e_inv, sb));
+            GEP_TRY(mm(gb, H, g.MH, g.LH, 0, N, 0, mt, 0, N, MM_QU, OP_STORE));   // V[:, 0:m)
+            return hipEventRecord(e_v, sb);
+        });
+    if (err == hipSuccess) err = invert(g, lv, [mt](const Node &n) { return n.a >= mt; });
+    if (err == hipSuccess && forked) err = hipStreamWaitEvent(st, e_inv, 0);
+    if (err == hipSuccess) err = invert(g, lv, [&top](const Node &n) { return n.a == top.a && n.b == top.b; });
+    if (err == hipSuccess) err = mm(g, H, g.MH, g.LH, 0, N, mt, N, 0, N, MM_QU, OP_STORE);  // V[:, m:N)
+    if (forked) {   // join the second stream even after an error
+        const hipError_t e = hipStreamWaitEvent(st, e_v, 0);
+        if (err == hipSuccess) err = e;
+    }
+    if (err == hipSuccess) err = mm(g, g.LH, g.MH, Ht, 0, N, 0, N, 0, N, MM_QU | MM_LOWER, OP_STORE);
+    if (e_split) (void)hipEventDestroy(e_split);
+    if (e_inv) (void)hipEventDestroy(e_inv);
+    if (e_v) (void)hipEventDestroy(e_v);
+    GEP_TRY(err);
     return launch_mirror1(Ht, N, st);
 }
 
