@@ -45,6 +45,12 @@ namespace {
 
 using MmCfg = TileCfg<128, 128, 16, 2, 4>;
 
+// Share of the compute units (in quarters) the work moved off the
+// factorization's critical path may occupy.
+#ifndef HS_GEP_BG_QUARTERS
+#define HS_GEP_BG_QUARTERS 3
+#endif
+
 // product flags
 constexpr int MM_PU = 1;      // P upper triangular: k <= row of C
 constexpr int MM_QL = 2;      // Q lower triangular: k >= column of C
@@ -688,14 +694,14 @@ hipError_t launch_gep(const double2 *H, const double2 *S, int N, double2 *L, dou
     }
     // Once the factorization has passed the top split m, the inverse of the
     // leading block [0, m) and the columns [0, m) of V = H MH depend on nothing
-    // still to come: they run on a second stream, with at most 3/4 of the
-    // compute units, beside the rest of the factorization. V is kept in LH,
+    // still to come: they run on a second stream, with at most HS_GEP_BG_QUARTERS / 4 of
+    // the compute units, beside the rest of the factorization. V is kept in LH,
     // whose columns < m the factorization no longer touches by then.
     const Node top = lv[0][0];
     const int mt = top.m;
     Gep gb = g;
     gb.st = sb;
-    gb.cap = num_cus() * 3 / 4;
+    gb.cap = num_cus() * HS_GEP_BG_QUARTERS / 4;
     hipEvent_t e_split = nullptr, e_inv = nullptr, e_v = nullptr;
     hipError_t err = hipEventCreateWithFlags(&e_split, hipEventDisableTiming);
     if (err == hipSuccess) err = hipEventCreateWithFlags(&e_inv, hipEventDisableTiming);
