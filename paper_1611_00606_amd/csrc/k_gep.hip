@@ -633,22 +633,30 @@ void tree(int a, int b, int depth, std::vector<std::vector<Node>> &lv) {
     tree(m, b, depth + 1, lv);
 }
 
+// The two products and the transpose of a set of independent nodes.
+hipError_t node_w21(const Gep &g, const std::vector<Node> &nodes) {   // W21 = L21 M11
+    std::vector<Rect> r;
+    for (const Node &n : nodes) r.push_back(Rect{n.m, n.b, n.a, n.m, n.a, n.m});
+    return mm_batch(g, g.LH, g.M, g.W, r.data(), (int)r.size(), MM_QL, OP_STORE);
+}
+hipError_t node_m21(const Gep &g, const std::vector<Node> &nodes) {   // M21 = -M22 W21, MH12
+    std::vector<Rect> r;
+    for (const Node &n : nodes) r.push_back(Rect{n.m, n.b, n.a, n.m, n.m, n.b});
+    GEP_TRY(mm_batch(g, g.MH, g.W, g.M, r.data(), (int)r.size(), MM_PU, OP_NEG));
+    for (const Node &n : nodes) GEP_TRY(conj_t(g, g.M, g.MH, n.m, n.b, n.a, n.m));
+    return hipSuccess;
+}
+
 template <class Keep>
 hipError_t invert(const Gep &g, const std::vector<std::vector<Node>> &lv, Keep keep) {
-    std::vector<Rect> r;
     std::vector<Node> nodes;
     for (int d = (int)lv.size() - 1; d >= 0; --d) {
         nodes.clear();
         for (const Node &n : lv[d])
             if (keep(n)) nodes.push_back(n);
         if (nodes.empty()) continue;
-        r.clear();
-        for (const Node &n : nodes) r.push_back(Rect{n.m, n.b, n.a, n.m, n.a, n.m});
-        GEP_TRY(mm_batch(g, g.LH, g.M, g.W, r.data(), (int)r.size(), MM_QL, OP_STORE));  // W21 = L21 M11
-        r.clear();
-        for (const Node &n : nodes) r.push_back(Rect{n.m, n.b, n.a, n.m, n.m, n.b});
-        GEP_TRY(mm_batch(g, g.MH, g.W, g.M, r.data(), (int)r.size(), MM_PU, OP_NEG));    // M21 = -M22 W21
-        for (const Node &n : nodes) GEP_TRY(conj_t(g, g.M, g.MH, n.m, n.b, n.a, n.m));    // MH12
+        GEP_TRY(node_w21(g, nodes));
+        GEP_TRY(node_m21(g, nodes));
     }
     return hipSuccess;
 }
@@ -693,8 +701,8 @@ hipError_t launch_gep(const double2 *H, const double2 *S, int N, double2 *L, dou
         return launch_mirror1(Ht, N, st);
     }
     // Once the factorization has passed the top split m, the inverse of the
-    // leading block [0, m) and the columns [0, m) of V = H MH depend on nothing
-    // still to come: they run on a second stream, with at most HS_GEP_BG_QUARTERS / 4 of
+    // leading block [0, m), the top split's W21 = L21 M11 and the columns
+    // [0, m) of V = H MH depend on nothing still to come: they run on a second stream, with at most HS_GEP_BG_QUARTERS / 4 of
     // the compute units, beside the rest of the factorization. V is kept in LH,
     // whose columns < m the factorization no longer touches by then.
     const Node top = lv[0][0];
@@ -715,13 +723,14 @@ hipError_t launch_gep(const double2 *H, const double2 *S, int N, double2 *L, dou
             GEP_TRY(hipStreamWaitEvent(sb, e_split, 0));
             forked = true;
             GEP_TRY(invert(gb, lv, left));
+            GEP_TRY(node_w21(gb, {top}));   // L21 and M11 of the top split are final too
             GEP_TRY(hipEventRecord(e_inv, sb));
             GEP_TRY(mm(gb, H, g.MH, g.LH, 0, N, 0, mt, 0, N, MM_QU, OP_STORE));   // V[:, 0:m)
             return hipEventRecord(e_v, sb);
         });
     if (err == hipSuccess) err = invert(g, lv, [mt](const Node &n) { return n.a >= mt; });
     if (err == hipSuccess && forked) err = hipStreamWaitEvent(st, e_inv, 0);
-    if (err == hipSuccess) err = invert(g, lv, [&top](const Node &n) { return n.a == top.a && n.b == top.b; });
+    if (err == hipSuccess) err = node_m21(g, {top});
     if (err == hipSuccess) err = mm(g, H, g.MH, g.LH, 0, N, mt, N, 0, N, MM_QU, OP_STORE);  // V[:, m:N)
     if (forked) {   // join the second stream even after an error
         const hipError_t e = hipStreamWaitEvent(st, e_v, 0);
