@@ -187,8 +187,9 @@ __global__ void __launch_bounds__(MmCfg::NT) k_gep_mm(const MmArgs args) {
 // sits in LDS as the 36 lower 16 x 16 tiles (rows XOR-swizzled, so that the
 // MFMA fragment loads and the accumulator stores hit distinct banks).
 //   factor, right-looking over 16-column panels P:
-//     wave 0: Cholesky of the diagonal tile and its inverse, in registers
-//             (lane r holds row r; values broadcast with readlane);
+//     wave 0: Cholesky of the diagonal tile in registers (lane r holds row
+//             r; values broadcast with readlane), then its inverse with the
+//             factor read back from LDS;
 //     panel:  L_IP = C_IP inv(L_PP)^H          one tile per wave, MFMA;
 //     update: C_IJ -= L_IP L_JP^H, P < J <= I   tiles spread over the waves.
 //   inverse X = L^{-1}, in place: every wave inverts one diagonal tile, then
@@ -235,20 +236,21 @@ __device__ __forceinline__ int chol16(double2 (&a)[16], int lane) {
     return inf;
 }
 
-// Lanes 0..15 hold the rows of a lower-triangular 16 x 16 factor; lane c
-// gets column c of its inverse (x_i = (delta_ic - sum_{k<i} l_ik x_k) / l_ii).
-__device__ __forceinline__ void inv16(const double2 (&a)[16], double2 (&x)[16], int lane) {
+// Column (lane & 15) of the inverse of the lower-triangular 16 x 16 tile D
+// (in LDS): x_i = (delta_ic - sum_{k<i} l_ik x_k) / l_ii, the factor read with
+// broadcast loads (the same address in every lane).
+__device__ __forceinline__ void inv16(const double2 *D, double2 (&x)[16], int lane) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-        double2 t = double2{lane == i ? 1.0 : 0.0, 0.0};
+        double2 t = double2{(lane & 15) == i ? 1.0 : 0.0, 0.0};
 #pragma unroll
         for (int k = 0; k < i; ++k) {
-            const double lx = bcast(a[k].x, i), ly = bcast(a[k].y, i);   // l_ik
-            t.x -= lx * x[k].x - ly * x[k].y;
-            t.y -= lx * x[k].y + ly * x[k].x;
+            const double2 l = D[lsw(i, k)];   // l_ik
+            t.x -= l.x * x[k].x - l.y * x[k].y;
+            t.y -= l.x * x[k].y + l.y * x[k].x;
         }
-        const double d = bcast(a[i].x, i);
-        x[i] = double2{t.x / d, t.y / d};
+        const double rd = 1.0 / D[lsw(i, i)].x;
+        x[i] = double2{t.x * rd, t.y * rd};
     }
 }
 
@@ -303,13 +305,19 @@ k_gep_leaf(double2 *__restrict__ L, double2 *__restrict__ M, double2 *__restrict
     const int lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
 
-    // stage: element (i, k), k <= i, of the padded block
-    for (int e = tid; e < LB * LB; e += 512) {
-        const int i = e / LB, k = e % LB;
-        if (k <= i) {
-            double2 v = double2{i == k ? 1.0 : 0.0, 0.0};
-            if (i < nb) v = L[(long long)(kb + i) * N + kb + k];
-            ltile(T, i >> 4, k >> 4)[lsw(i & 15, k & 15)] = v;
+    // stage: element (i, k), k <= i, of the padded block (loads issued together)
+    for (int c = 0; c < LB * LB / 512; c += 8) {
+        double2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = tid + 512 * (c + u), i = e / LB, k = e % LB;
+            v[u] = double2{i == k ? 1.0 : 0.0, 0.0};
+            if (k <= i && i < nb) v[u] = L[(long long)(kb + i) * N + kb + k];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = tid + 512 * (c + u), i = e / LB, k = e % LB;
+            if (k <= i) ltile(T, i >> 4, k >> 4)[lsw(i & 15, k & 15)] = v[u];
         }
     }
     __syncthreads();
@@ -324,10 +332,12 @@ k_gep_leaf(double2 *__restrict__ L, double2 *__restrict__ M, double2 *__restrict
             for (int k = 0; k < 16; ++k) a[k] = D[lsw(r, k)];
             const int f = chol16(a, lane);
             if (f != 0 && inf == 0 && 16 * P + f <= nb) inf = 16 * P + f;
-            inv16(a, x, lane);
             if (lane < 16) {
 #pragma unroll
                 for (int k = 0; k < 16; ++k) D[lsw(lane, k)] = a[k];
+            }
+            inv16(D, x, lane);   // one wave: its LDS accesses complete in order
+            if (lane < 16) {
 #pragma unroll
                 for (int i = 0; i < 16; ++i) Ti[lsw(i, lane)] = x[i];
             }
@@ -373,11 +383,8 @@ k_gep_leaf(double2 *__restrict__ L, double2 *__restrict__ M, double2 *__restrict
     // inverse: diagonal tiles, one per wave
     {
         double2 *D = ltile(T, w, w);
-        double2 a[16], x[16];
-        const int r = lane & 15;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) a[k] = D[lsw(r, k)];
-        inv16(a, x, lane);
+        double2 x[16];
+        inv16(D, x, lane);
         if (lane < 16) {
 #pragma unroll
             for (int i = 0; i < 16; ++i) D[lsw(i, lane)] = i >= lane ? x[i] : double2{0.0, 0.0};
