@@ -236,7 +236,7 @@ int hs_autotune_atoms(const int32_t *nl_values, int n_values, int N_G, int reps,
  * complex FP64 MFMA tiles.
  * ---------------------------------------------------------------------- */
 
-/* Device scratch hs_gep_reduce needs for N (0 for N < 1): 4 N^2 complex. */
+/* Device scratch hs_gep_reduce needs for N (0 for N < 1): 5 N^2 complex. */
 size_t hs_gep_workspace_bytes(int N);
 
 /*

@@ -57,6 +57,8 @@ constexpr int MM_QL = 2;      // Q lower triangular: k >= column of C
 constexpr int MM_QU = 4;      // Q upper triangular: k <= column of C
 constexpr int MM_LOWER = 8;   // only C's lower triangle (square region)
 constexpr int MM_MASK = 16;   // only elements on or below the diagonal (any region)
+constexpr int MM_PL = 32;     // P lower triangular: k >= row of C
+constexpr int MM_UPPER = 64;  // only C's upper triangle (square region); zeros below it
 // epilogue
 constexpr int OP_STORE = 0, OP_NEG = 1, OP_SUB = 2;
 
@@ -72,6 +74,7 @@ constexpr int MM_JOBS = 32;
 
 struct MmArgs {
     const double2 *P, *Q;
+    const double2 *P2, *Q2;   // second term, same rectangle and contraction range
     double2 *C;
     int N;                    // leading dimension of P, Q, C
     int flags, op;
@@ -83,6 +86,7 @@ struct MmArgs {
 // C[i][j] (op)= sum_k conj(P[k][i]) Q[k][j] over each job's rectangle, in
 // absolute indices; the triangular flags trim each tile's contraction range
 // to the rows where both operands can be nonzero.
+template <int NSEG>
 __device__ __forceinline__ void mm_tile(const MmArgs &args, int tile, double2 *lds) {
     using Cfg = MmCfg;
     const int flags = args.flags;
@@ -98,7 +102,13 @@ __device__ __forceinline__ void mm_tile(const MmArgs &args, int tile, double2 *l
     // Tiles whose contraction is longest go first (the triangular flags
     // make it depend on the tile row or column).
     int ti, tj;
-    if (flags & MM_LOWER) {   // lower triangle, tj <= ti
+    if (flags & MM_UPPER) {   // upper triangle, tj >= ti, by diagonals from the far corner
+        int r = (int)((sqrt(8.0 * bid + 1.0) - 1.0) * 0.5);
+        while ((r + 1) * (r + 2) / 2 <= bid) ++r;
+        while (r * (r + 1) / 2 > bid) --r;
+        ti = bid - r * (r + 1) / 2;
+        tj = ti + ntr - 1 - r;
+    } else if (flags & MM_LOWER) {   // lower triangle, tj <= ti
         const bool byc = flags & MM_QU;   // contraction grows with tj: last columns first
         const int t = byc ? bid : ntr * (ntr + 1) / 2 - 1 - bid;
         int r = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
@@ -111,6 +121,19 @@ __device__ __forceinline__ void mm_tile(const MmArgs &args, int tile, double2 *l
             ti = r;
             tj = t - r * (r + 1) / 2;
         }
+    } else if ((flags & MM_PL) && (flags & MM_QU)) {   // longest: largest tj - ti first
+        int rem = bid, c = ntc - 1;
+        for (;; --c) {   // diagonals tj - ti = c, from the far corner
+            const int lo = c < 0 ? -c : 0;
+            const int hi = ntr < ntc - c ? ntr : ntc - c;
+            const int cnt = hi > lo ? hi - lo : 0;
+            if (rem < cnt || c <= -ntr) {
+                ti = lo + rem;
+                break;
+            }
+            rem -= cnt;
+        }
+        tj = ti + c;
     } else if (flags & MM_PU) {   // longest: last tile rows
         ti = ntr - 1 - bid / ntc;
         tj = bid % ntc;
@@ -128,14 +151,20 @@ __device__ __forceinline__ void mm_tile(const MmArgs &args, int tile, double2 *l
     if (flags & MM_PU) khi = min(khi, m0 + Cfg::BM);
     if (flags & MM_QU) khi = min(khi, n0 + Cfg::BN);
     if (flags & MM_QL) klo = max(klo, n0);
+    if (flags & MM_PL) klo = max(klo, m0);
 
-    Segs<1, false, false> t;
-    t.nseg = 1;
+    Segs<NSEG, false, false> t;
+    t.nseg = NSEG;
     t.len = khi > klo ? khi - klo : 0;
     t.ldp = N;
     t.ldq = N;
-    t.P[0] = args.P + (long long)(t.len ? klo : 0) * N;
-    t.Q[0] = args.Q + (long long)(t.len ? klo : 0) * N;
+    const long long k0 = (long long)(t.len ? klo : 0) * N;
+    t.P[0] = args.P + k0;
+    t.Q[0] = args.Q + k0;
+    if constexpr (NSEG == 2) {
+        t.P[1] = args.P2 + k0;
+        t.Q[1] = args.Q2 + k0;
+    }
     t.palt = nullptr;
     t.sel = nullptr;
     t.qscale = nullptr;
@@ -143,6 +172,7 @@ __device__ __forceinline__ void mm_tile(const MmArgs &args, int tile, double2 *l
     ztile_direct<Cfg>(t, m0, i1, n0, j1, acc, lds);
 
     const bool lower = flags & (MM_LOWER | MM_MASK);
+    const bool upper = flags & MM_UPPER;
     const int op = args.op;
     double2 *C = args.C;
 #pragma unroll
@@ -155,7 +185,8 @@ __device__ __forceinline__ void mm_tile(const MmArgs &args, int tile, double2 *l
                 const int gp = m0 + acc_row<Cfg>(i, v);
                 if (gp < i1 && g < j1 && (!lower || g <= gp)) {
                     double2 *o = C + (long long)gp * N + g;
-                    const double re = acc.re[i][j][v], im = acc.im[i][j][v];
+                    const bool z = upper && g < gp;
+                    const double re = z ? 0.0 : acc.re[i][j][v], im = z ? 0.0 : acc.im[i][j][v];
                     if (op == OP_SUB) {
                         double2 r = *o;
                         r.x -= re;
@@ -173,10 +204,11 @@ __device__ __forceinline__ void mm_tile(const MmArgs &args, int tile, double2 *l
 
 // Blocks loop over the tiles (a launch may have fewer blocks than tiles when
 // it runs beside latency-critical work).
+template <int NSEG>
 __global__ void __launch_bounds__(MmCfg::NT) k_gep_mm(const MmArgs args) {
     __shared__ double2 lds[MmCfg::LDS_ELEMS];
     for (int tile = blockIdx.x; tile < args.total; tile += gridDim.x) {
-        mm_tile(args, tile, lds);
+        mm_tile<NSEG>(args, tile, lds);
         __syncthreads();   // LDS is reused by the next tile
     }
 }
@@ -434,16 +466,28 @@ k_gep_leaf(double2 *__restrict__ L, double2 *__restrict__ M, double2 *__restrict
     }
 }
 
-// L := lower(S) (upper triangle zero), M := 0, MH := 0
+// L := lower(S) (upper triangle zero), M := 0, MH := 0, LH := 0 below the
+// diagonal, HL := lower(H) with half its diagonal (so that H = HL + HL^H)
 __global__ void __launch_bounds__(256)
-k_gep_init(const double2 *__restrict__ S, double2 *__restrict__ L, double2 *__restrict__ M,
-           double2 *__restrict__ MH, int N) {
+k_gep_init(const double2 *__restrict__ H, const double2 *__restrict__ S, double2 *__restrict__ L,
+           double2 *__restrict__ M, double2 *__restrict__ MH, double2 *__restrict__ LH,
+           double2 *__restrict__ HL, int N) {
     const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
     if (e >= (long long)N * N) return;
     const int i = (int)(e / N), j = (int)(e % N);
-    L[e] = j <= i ? S[e] : double2{0.0, 0.0};
-    M[e] = double2{0.0, 0.0};
-    MH[e] = double2{0.0, 0.0};
+    const double2 z = double2{0.0, 0.0};
+    double2 sv = z;
+    if (j <= i) sv = S[e];
+    L[e] = sv;
+    M[e] = z;
+    MH[e] = z;
+    if (j < i) LH[e] = z;
+    if (HL) {
+        double2 hv = z;
+        if (j <= i) hv = H[e];
+        if (j == i) hv = double2{0.5 * hv.x, 0.0};
+        HL[e] = hv;
+    }
 }
 
 __global__ void k_gep_info_clear(int *info) { *info = 0; }
@@ -472,7 +516,7 @@ k_gep_conj_t(const double2 *__restrict__ X, double2 *__restrict__ D, int N, int 
 }
 
 struct Gep {
-    double2 *L, *LH, *M, *MH, *W;
+    double2 *L, *LH, *M, *MH, *W, *HL;
     int N;
     int *info;
     hipStream_t st;
@@ -491,12 +535,15 @@ struct Rect {
 
 // Products over the rectangles r[0 .. n), up to MM_JOBS per launch.
 hipError_t mm_batch(const Gep &g, const double2 *P, const double2 *Q, double2 *C, const Rect *r,
-                    int n, int flags, int op) {
+                    int n, int flags, int op, const double2 *P2 = nullptr,
+                    const double2 *Q2 = nullptr) {
     using Cfg = MmCfg;
     for (int b = 0; b < n; b += MM_JOBS) {
         MmArgs a = {};
         a.P = P;
         a.Q = Q;
+        a.P2 = P2;
+        a.Q2 = Q2;
         a.C = C;
         a.N = g.N;
         a.flags = flags;
@@ -514,7 +561,7 @@ hipError_t mm_batch(const Gep &g, const double2 *P, const double2 *Q, double2 *C
             j.ntr = (j.i1 - j.i0 + Cfg::BM - 1) / Cfg::BM;
             j.ntc = (j.j1 - j.j0 + Cfg::BN - 1) / Cfg::BN;
             j.start = (int)nblk;
-            if (flags & MM_LOWER) {
+            if (flags & (MM_LOWER | MM_UPPER)) {
                 if (j.i0 != j.j0 || j.i1 != j.j1) return hipErrorInvalidValue;
                 nblk += (long long)j.ntr * (j.ntr + 1) / 2;
             } else {
@@ -524,7 +571,10 @@ hipError_t mm_batch(const Gep &g, const double2 *P, const double2 *Q, double2 *C
         if (a.njobs == 0) continue;
         a.total = (int)nblk;
         const long long grid = g.cap > 0 && nblk > g.cap ? g.cap : nblk;
-        hipLaunchKernelGGL(k_gep_mm, dim3((unsigned)grid), dim3(Cfg::NT), 0, g.st, a);
+        if (P2)
+            hipLaunchKernelGGL(k_gep_mm<2>, dim3((unsigned)grid), dim3(Cfg::NT), 0, g.st, a);
+        else
+            hipLaunchKernelGGL(k_gep_mm<1>, dim3((unsigned)grid), dim3(Cfg::NT), 0, g.st, a);
         GEP_TRY(hipGetLastError());
     }
     return hipSuccess;
@@ -670,14 +720,47 @@ hipError_t invert(const Gep &g, const std::vector<std::vector<Node>> &lv, Keep k
 
 size_t padded(size_t bytes) { return (bytes + 255) / 256 * 256; }
 
+// With H = HL + HL^H (HL: lower triangle of H, half its diagonal),
+//   Ht = M H M^H = A B^H + B A^H,  A = M HL (lower), B = M,
+// so Ht takes WH = A^H = HL^H MH (upper: WH[i][j] sums k in [i, j]) and the
+// two-term lower-triangle product Ht = WH^H MH + MH^H WH (k <= j). WH is
+// kept in LH, whose lower triangle is zero.
+
+// Below this size the two-term form has too few lower-triangle tiles to fill
+// the device, and Ht = V^H MH with V = H MH (N^3/2 + N^3/6 complex
+// multiply-adds over full squares of tiles) is faster.
+constexpr int GEP_HER2K_MIN_N = 4096;
+
+// V[:, c0:c1) = H MH[:, c0:c1), kept in LH
+hipError_t v_cols(const Gep &g, const double2 *H, int c0, int c1) {
+    return mm(g, H, g.MH, g.LH, 0, g.N, c0, c1, 0, g.N, MM_QU, OP_STORE);
+}
+
+// WH[:, c0:c1) (rows i <= j)
+hipError_t wh_cols(const Gep &g, int c0, int c1) {
+    const int N = g.N;
+    GEP_TRY(mm(g, g.HL, g.MH, g.LH, 0, c0, c0, c1, 0, N, MM_PL | MM_QU, OP_STORE));
+    return mm(g, g.HL, g.MH, g.LH, c0, c1, c0, c1, 0, N, MM_PL | MM_QU | MM_UPPER, OP_STORE);
+}
+
+// lower triangle of Ht, rows [r0, r1)
+hipError_t her2k_rows(const Gep &g, double2 *Ht, int r0, int r1) {
+    const int N = g.N;
+    const Rect rect = {r0, r1, 0, r0, 0, N};
+    const Rect tri = {r0, r1, r0, r1, 0, N};
+    GEP_TRY(mm_batch(g, g.LH, g.MH, Ht, &rect, 1, MM_QU, OP_STORE, g.MH, g.LH));
+    return mm_batch(g, g.LH, g.MH, Ht, &tri, 1, MM_QU | MM_LOWER, OP_STORE, g.MH, g.LH);
+}
+
 }  // namespace
 
 size_t gep_workspace_bytes(int N) {
-    return 4 * padded(16 * (size_t)N * (size_t)N) + 256;   // LH, M, MH, W, info slot
+    return 5 * padded(16 * (size_t)N * (size_t)N) + 256;   // LH, M, MH, W, HL, info slot
 }
 
 hipError_t launch_gep(const double2 *H, const double2 *S, int N, double2 *L, double2 *Ht,
                       int *info, char *ws, hipStream_t st) {
+    const bool two = N >= GEP_HER2K_MIN_N;   // Ht from WH (two-term product), else from V
     const size_t m = padded(16 * (size_t)N * (size_t)N);
     Gep g;
     g.L = L;
@@ -685,12 +768,13 @@ hipError_t launch_gep(const double2 *H, const double2 *S, int N, double2 *L, dou
     g.M = reinterpret_cast<double2 *>(ws + m);
     g.MH = reinterpret_cast<double2 *>(ws + 2 * m);
     g.W = reinterpret_cast<double2 *>(ws + 3 * m);
+    g.HL = reinterpret_cast<double2 *>(ws + 4 * m);
     g.N = N;
-    g.info = info ? info : reinterpret_cast<int *>(ws + 4 * m);
+    g.info = info ? info : reinterpret_cast<int *>(ws + 5 * m);
     g.st = st;
     const long long nn = (long long)N * N;
-    hipLaunchKernelGGL(k_gep_init, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, S, L, g.M,
-                       g.MH, N);
+    hipLaunchKernelGGL(k_gep_init, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, H, S, L,
+                       g.M, g.MH, g.LH, two ? g.HL : nullptr, N);
     GEP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_gep_info_clear, dim3(1), dim3(1), 0, st, g.info);
     GEP_TRY(hipGetLastError());
@@ -703,15 +787,20 @@ hipError_t launch_gep(const double2 *H, const double2 *S, int N, double2 *L, dou
     if (!sb) {
         GEP_TRY(factor(g, [](int) { return hipSuccess; }));
         GEP_TRY(invert(g, lv, all));
-        GEP_TRY(mm(g, H, g.MH, g.LH, 0, N, 0, N, 0, N, MM_QU, OP_STORE));              // V = H MH
-        GEP_TRY(mm(g, g.LH, g.MH, Ht, 0, N, 0, N, 0, N, MM_QU | MM_LOWER, OP_STORE));  // Ht = V^H MH
+        if (two) {
+            GEP_TRY(wh_cols(g, 0, N));
+            GEP_TRY(her2k_rows(g, Ht, 0, N));
+        } else {
+            GEP_TRY(v_cols(g, H, 0, N));
+            GEP_TRY(mm(g, g.LH, g.MH, Ht, 0, N, 0, N, 0, N, MM_QU | MM_LOWER, OP_STORE));  // V^H MH
+        }
         return launch_mirror1(Ht, N, st);
     }
     // Once the factorization has passed the top split m, the inverse of the
-    // leading block [0, m), the top split's W21 = L21 M11 and the columns
-    // [0, m) of V = H MH depend on nothing still to come: they run on a second stream, with at most HS_GEP_BG_QUARTERS / 4 of
-    // the compute units, beside the rest of the factorization. V is kept in LH,
-    // whose columns < m the factorization no longer touches by then.
+    // leading block [0, m), the top split's W21 = L21 M11, WH[:, 0:m) and the
+    // rows [0, m) of Ht (or V[:, 0:m)) depend on nothing still to come: they run on a second
+    // stream, with at most HS_GEP_BG_QUARTERS / 4 of the compute units, beside
+    // the rest of the factorization (which no longer touches LH's columns < m).
     const Node top = lv[0][0];
     const int mt = top.m;
     Gep gb = g;
@@ -732,18 +821,25 @@ hipError_t launch_gep(const double2 *H, const double2 *S, int N, double2 *L, dou
             GEP_TRY(invert(gb, lv, left));
             GEP_TRY(node_w21(gb, {top}));   // L21 and M11 of the top split are final too
             GEP_TRY(hipEventRecord(e_inv, sb));
-            GEP_TRY(mm(gb, H, g.MH, g.LH, 0, N, 0, mt, 0, N, MM_QU, OP_STORE));   // V[:, 0:m)
+            if (two) {
+                GEP_TRY(wh_cols(gb, 0, mt));
+                GEP_TRY(her2k_rows(gb, Ht, 0, mt));
+            } else {
+                GEP_TRY(v_cols(gb, H, 0, mt));
+            }
             return hipEventRecord(e_v, sb);
         });
     if (err == hipSuccess) err = invert(g, lv, [mt](const Node &n) { return n.a >= mt; });
     if (err == hipSuccess && forked) err = hipStreamWaitEvent(st, e_inv, 0);
     if (err == hipSuccess) err = node_m21(g, {top});
-    if (err == hipSuccess) err = mm(g, H, g.MH, g.LH, 0, N, mt, N, 0, N, MM_QU, OP_STORE);  // V[:, m:N)
+    if (err == hipSuccess) err = two ? wh_cols(g, mt, N) : v_cols(g, H, mt, N);
     if (forked) {   // join the second stream even after an error
         const hipError_t e = hipStreamWaitEvent(st, e_v, 0);
         if (err == hipSuccess) err = e;
     }
-    if (err == hipSuccess) err = mm(g, g.LH, g.MH, Ht, 0, N, 0, N, 0, N, MM_QU | MM_LOWER, OP_STORE);
+    if (err == hipSuccess)
+        err = two ? her2k_rows(g, Ht, mt, N)
+                  : mm(g, g.LH, g.MH, Ht, 0, N, 0, N, 0, N, MM_QU | MM_LOWER, OP_STORE);
     if (e_split) (void)hipEventDestroy(e_split);
     if (e_inv) (void)hipEventDestroy(e_inv);
     if (e_v) (void)hipEventDestroy(e_v);

@@ -81,6 +81,14 @@ def test_random_pairs(N):
     _check(H, S, *_gep_gpu(H, S))
 
 
+def test_two_term_form_against_the_oracle():
+    """N >= 4096 takes the form Ht = WH^H MH + MH^H WH (H split into its lower
+    triangle and that triangle's conjugate transpose): full comparison at a
+    size past the switch, with a ragged last panel."""
+    H, S = _random_pair(4200, seed=42)
+    _check(H, S, *_gep_gpu(H, S))
+
+
 def test_eigenvalues_match_generalized_problem():
     """Ht has the generalized eigenvalues of (H, S): the point of the reduction."""
     H, S = _random_pair(200, seed=7, shift=20.0)
