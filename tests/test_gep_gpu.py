@@ -89,6 +89,38 @@ def test_two_term_form_against_the_oracle():
     _check(H, S, *_gep_gpu(H, S))
 
 
+@pytest.mark.parametrize("cond", [1e4, 1e8])
+def test_ill_conditioned_overlap(cond):
+    """S with singular values spread over [1/cond, 1] (the paper's overlaps are
+    positive definite up to a few very small singular values). Two correct
+    FP64 orders of the reduction differ in Ht by about cond(S) u (u = 2^-53)
+    and in L by about cond(S)^{1/2} u, so the comparison with the oracle uses
+    10 cond(S) u for Ht and 10 N cond(S)^{1/2} u for L; the backward
+    residuals do not grow with cond(S) for S = L L^H (1e-13) and grow with
+    cond(L) = cond(S)^{1/2} for L Ht L^H = H (100 cond(S)^{1/2} u)."""
+    u = 2.0 ** -53
+    N = 600
+    rng = np.random.default_rng(int(np.log10(cond)))
+    Q, _ = np.linalg.qr(cn(rng, (N, N)))
+    sv = np.logspace(0.0, -np.log10(cond), N)
+    S = (Q * sv) @ Q.conj().T
+    S = 0.5 * (S + S.conj().T)
+    B = cn(rng, (N, N))
+    H = B + B.conj().T
+    L, Ht, info = _gep_gpu(H, S)
+    L0, Ht0, inf0 = O.gep_reduce(H, S)
+    assert info == 0 and inf0 == 0
+    eL, eH = _rel(L, L0), _rel(Ht, Ht0)
+    rS = np.linalg.norm(L @ L.conj().T - S) / np.linalg.norm(S)
+    rH = np.linalg.norm(L @ Ht @ L.conj().T - H) / np.linalg.norm(H)
+    print(f"  cond {cond:.0e}: L {eL:.2e} Ht {eH:.2e} res S {rS:.2e} res H {rH:.2e}", flush=True)
+    assert eL <= 10 * N * np.sqrt(cond) * u
+    assert eH <= 10 * cond * u
+    assert rS <= 1e-13
+    assert rH <= 100 * np.sqrt(cond) * u
+    assert np.array_equal(Ht, Ht.conj().T)
+
+
 def test_eigenvalues_match_generalized_problem():
     """Ht has the generalized eigenvalues of (H, S): the point of the reduction."""
     H, S = _random_pair(200, seed=7, shift=20.0)
