@@ -119,8 +119,9 @@ typedef struct {
 typedef struct {
     /* hipStream_t to enqueue on; NULL = the default (null) stream. */
     void *stream;
-    /* device scratch of >= hs_workspace_bytes(...) bytes, 256-byte aligned,
-       owned by the caller; contents on entry are ignored. */
+    /* device scratch of >= hs_workspace_bytes(...) bytes, 16-byte aligned
+       (256 recommended; otherwise hs_build_ex returns -12), owned by the
+       caller; contents on entry are ignored. */
     void *workspace;
     size_t workspace_bytes;
     /* device int32 [N_A] or NULL. On completion info[a] = 0 when T_AA_a had a
@@ -232,8 +233,8 @@ int hs_autotune_atoms(const int32_t *nl_values, int n_values, int N_G, int reps,
  *     S = L L^H   (Cholesky; L lower with a positive real diagonal)
  *     Ht = L^{-1} H L^{-H}
  * H c = lambda S c holds exactly when Ht y = lambda y with y = L^H c.
- * Recursive, with 64 x 64 leaves; the O(N^3) work runs as products on the
- * complex FP64 MFMA tiles.
+ * Right-looking over 128-column panels with an explicit inverse of L; the
+ * O(N^3) work runs as products on the complex FP64 MFMA tiles.
  * ---------------------------------------------------------------------- */
 
 /* Device scratch hs_gep_reduce needs for N (0 for N < 1): 5 N^2 complex. */
@@ -251,11 +252,11 @@ size_t hs_gep_workspace_bytes(int N);
  *   6 info  device int32 or NULL: 0, or the 1-based index of the first
  *         pivot of S that is not > 0 or is NaN (LAPACK zpotrf); L and Ht
  *         are undefined then
- *   7 workspace  device, >= hs_gep_workspace_bytes(N) bytes, 256-byte
- *         aligned;  8 workspace_bytes;  9 stream
+ *   7 workspace  device, >= hs_gep_workspace_bytes(N) bytes, 16-byte
+ *         aligned (256 recommended);  8 workspace_bytes;  9 stream
  * Outputs must not overlap the inputs or each other. Returns 0, -i for an
- * invalid argument i (NULL pointer, N < 1), 2 (workspace too small), or 1
- * (HIP error).
+ * invalid argument i (NULL pointer, N < 1, workspace not 16-byte aligned),
+ * 2 (workspace too small), or 1 (HIP error).
  * For N > 384 part of the work runs on up to two library-owned streams of the
  * same device (created on first use, default priority, kept until the process
  * ends), forked from and joined back into `stream` with events: when the call

@@ -344,6 +344,7 @@ int hs_build_ex(const hs_complex *A, const hs_complex *B, const hs_complex *T_AA
     if (rc != 0) return rc;
     if (opt->batch && !hs::BatchPlan::valid(p, opt->tuning ? opt->tuning->cfg : nullptr))
         return -12;
+    if (reinterpret_cast<uintptr_t>(opt->workspace) % 16) return -12;   // 16-byte loads
     rc = hs::check_device();
     if (rc != HS_OK) return rc;
     if (!opt->workspace || opt->workspace_bytes < p.atom_bytes() + p.kpoint_bytes(N_G, opt->mode))
@@ -390,7 +391,7 @@ int hs_gep_reduce(const hs_complex *H, const hs_complex *S, int N, hs_complex *L
     if (N < 1) return -3;
     if (!L) return -4;
     if (!Ht) return -5;
-    if (!workspace) return -7;
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 16) return -7;
     int rc = hs::check_device();
     if (rc != HS_OK) return rc;
     if (workspace_bytes < hs::gep_workspace_bytes(N)) return HS_ERR_WORKSPACE;

@@ -97,6 +97,10 @@ def test_build_ex_option_checks():
     opt = Bd.hs_options()
     opt.nl_per_atom = nl.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
     assert lib.hs_build_ex(*[FAKE] * 6, 2, 0, 8, FAKE, FAKE, ctypes.byref(opt)) == -8
+    opt = Bd.hs_options()
+    opt.workspace = FAKE + 8   # not 16-byte aligned
+    opt.workspace_bytes = 1 << 40
+    assert lib.hs_build_ex(*[FAKE] * 6, 2, 4, 8, FAKE, FAKE, ctypes.byref(opt)) == -12
 
 
 def test_status_strings():
@@ -209,7 +213,8 @@ def test_gep_argument_checks():
     assert P.hs_gep_workspace_bytes(0) == 0
     assert P.hs_gep_workspace_bytes(100) >= 2 * 16 * 100 * 100
     args = [FAKE, FAKE, 8, FAKE, FAKE, None, FAKE, 1 << 20, None]
-    for pos, bad in ((0, None), (1, None), (2, 0), (3, None), (4, None), (6, None)):
+    for pos, bad in ((0, None), (1, None), (2, 0), (3, None), (4, None), (6, None),
+                     (6, FAKE + 8)):
         a = list(args)
         a[pos] = bad
         assert lib.hs_gep_reduce(*a) == -(pos + 1)
