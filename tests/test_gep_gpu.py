@@ -268,3 +268,43 @@ def test_full_size_residuals():
         err = np.linalg.norm(got - col) / np.linalg.norm(col)
         print(f"  column {j} rel err {err:.2e}", flush=True)
         assert err <= TOL
+
+
+def test_largest_size_residuals():
+    """N = 16000: the inverse's recursion has 64 nodes at one depth, more than
+    one batched launch holds, and the workspace is 20 GB. The outputs satisfy
+    S = L L^H and H = L Ht L^H to backward-error level (complex128 products
+    on the device) and a few columns of Ht match the definition."""
+    from paper_1611_00606_amd import hs_gep_reduce
+    torch = _torch()
+    N = 16000
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev).manual_seed(16000)
+    A = torch.randn(N, N, dtype=torch.complex128, device=dev, generator=g)
+    S = A @ A.conj().T / N + torch.eye(N, dtype=torch.complex128, device=dev)
+    S = 0.5 * (S + S.conj().T)
+    H = torch.randn(N, N, dtype=torch.complex128, device=dev, generator=g)
+    H = H + H.conj().T
+    del A
+    L = torch.empty_like(S)
+    Ht = torch.empty_like(S)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    print(f"gep N={N}", flush=True)
+    hs_gep_reduce(H, S, L, Ht, info=info)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    r1 = torch.linalg.matrix_norm(L @ L.conj().T - S) / torch.linalg.matrix_norm(S)
+    r2 = torch.linalg.matrix_norm(L @ Ht @ L.conj().T - H) / torch.linalg.matrix_norm(H)
+    print(f"  residual S {r1.item():.2e} H {r2.item():.2e}", flush=True)
+    assert r1.item() <= 1e-13 and r2.item() <= 1e-12
+    assert torch.equal(Ht, Ht.conj().T)
+    assert torch.count_nonzero(torch.triu(L, 1)).item() == 0
+    Lc = L.cpu().numpy()
+    for j in (0, 8191, N - 1):
+        e = np.zeros(N, np.complex128)
+        e[j] = 1.0
+        hcol = (H @ torch.from_numpy(sl.solve_triangular(Lc, e, lower=True, trans="C")).to(dev)).cpu().numpy()
+        col = sl.solve_triangular(Lc, hcol, lower=True)
+        err = np.linalg.norm(Ht[:, j].cpu().numpy() - col) / np.linalg.norm(col)
+        print(f"  column {j} rel err {err:.2e}", flush=True)
+        assert err <= TOL
