@@ -593,12 +593,12 @@ hipError_t conj_t(const Gep &g, const double2 *X, double2 *D, int i0, int i1, in
     return hipGetLastError();
 }
 
-// Auxiliary streams per device (index 0: the factorization's lookahead,
-// 1: work moved off the critical path); default priority, created once and
-// kept for the life of the process.
+// Auxiliary streams per device (0: the factorization's lookahead, 1: work
+// moved off the critical path, 2: the panels' transposes); default priority,
+// created once and kept for the life of the process.
 hipStream_t aux_stream(int which) {
     static std::mutex mu;
-    static hipStream_t cached[64][2] = {};
+    static hipStream_t cached[64][3] = {};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
     std::lock_guard<std::mutex> lk(mu);
@@ -613,27 +613,43 @@ hipStream_t aux_stream(int which) {
 // Cholesky, right-looking over panels of LB columns: factor and invert the
 // diagonal block, then the panel L21 = S21 L11^{-H} (as LH21 = M11 S21^H) and
 // the update of the trailing lower triangle S22 -= L21 L21^H.
-// Lookahead (from 4 panels on): the update is split into the next column
-// block, applied on the caller's stream, and the rest, applied on an
-// auxiliary stream, so that the next panel's leaf, transposes and panel
-// product overlap the bulk of the update. The next column block's update
-// waits for the previous bulk update (both write that block); the bulk
-// update waits for the panel it applies.
+// Lookahead (from 4 panels on), with three streams:
+//   caller's    leaf, panel product, update of the next column block;
+//   lookahead   L21 = LH21^H (an output only), then the bulk of the update,
+//               beside the next leaf and panel;
+//   transposes  the next panel's S21^H, beside the next leaf.
+// The next column block's update waits for the previous bulk update (both
+// write that block); the bulk update and L21 wait for the panel they use;
+// the next S21^H waits for the next column block's update.
 template <class Hook>
 hipError_t factor(const Gep &g, Hook after_leaf) {
     const int N = g.N;
     const int np = (N + LB - 1) / LB;
-    Gep ga = g;
-    hipEvent_t e_panel = nullptr, e_bulk = nullptr;
+    Gep ga = g, gc = g;
+    hipEvent_t e_panel = nullptr, e_bulk = nullptr, e_next = nullptr, e_w = nullptr;
     bool ahead = np >= 4;
     if (ahead) {
         ga.st = aux_stream(0);
-        ahead = ga.st != nullptr &&
+        gc.st = aux_stream(2);
+        ahead = ga.st != nullptr && gc.st != nullptr &&
                 hipEventCreateWithFlags(&e_panel, hipEventDisableTiming) == hipSuccess &&
-                hipEventCreateWithFlags(&e_bulk, hipEventDisableTiming) == hipSuccess;
+                hipEventCreateWithFlags(&e_bulk, hipEventDisableTiming) == hipSuccess &&
+                hipEventCreateWithFlags(&e_next, hipEventDisableTiming) == hipSuccess &&
+                hipEventCreateWithFlags(&e_w, hipEventDisableTiming) == hipSuccess;
     }
-    bool bulk_pending = false;   // e_bulk recorded (no wait on an unrecorded event)
+    // recorded events still to be waited for (no wait on an unrecorded event)
+    bool bulk_pending = false, w_pending = false;
     hipError_t err = hipSuccess;
+    // S21^H of the first panel, beside the first leaf
+    const auto next_s21h = [&](int c0, int c1) -> hipError_t {   // columns [c0, c1)
+        GEP_TRY(hipEventRecord(e_next, g.st));
+        GEP_TRY(hipStreamWaitEvent(gc.st, e_next, 0));
+        GEP_TRY(conj_t(gc, g.L, g.W, c1, N, c0, c1));
+        GEP_TRY(hipEventRecord(e_w, gc.st));
+        w_pending = true;
+        return hipSuccess;
+    };
+    if (ahead) err = next_s21h(0, LB);
     for (int kb = 0; kb < N && err == hipSuccess; kb += LB) {
         const int nb = N - kb < LB ? N - kb : LB;
         const int t0 = kb + nb;
@@ -641,34 +657,44 @@ hipError_t factor(const Gep &g, Hook after_leaf) {
                            g.info);
         if ((err = hipGetLastError()) != hipSuccess) break;
         if ((err = after_leaf(t0)) != hipSuccess || t0 >= N) break;
-        if ((err = conj_t(g, g.L, g.W, t0, N, kb, t0)) != hipSuccess) break;     // W = S21^H
-        if ((err = mm(g, g.MH, g.W, g.LH, kb, t0, t0, N, kb, t0, MM_PU, OP_STORE)) != hipSuccess)
-            break;                                                                // LH21 = M11 S21^H
-        if ((err = conj_t(g, g.LH, g.L, kb, t0, t0, N)) != hipSuccess) break;    // L21
         if (!ahead) {
-            err = mm(g, g.LH, g.LH, g.L, t0, N, t0, N, kb, t0, MM_LOWER, OP_SUB); // S22 -= L21 L21^H
+            if ((err = conj_t(g, g.L, g.W, t0, N, kb, t0)) != hipSuccess) break;  // W = S21^H
+            if ((err = mm(g, g.MH, g.W, g.LH, kb, t0, t0, N, kb, t0, MM_PU, OP_STORE)) !=
+                hipSuccess)
+                break;                                                             // LH21 = M11 S21^H
+            if ((err = conj_t(g, g.LH, g.L, kb, t0, t0, N)) != hipSuccess) break; // L21
+            err = mm(g, g.LH, g.LH, g.L, t0, N, t0, N, kb, t0, MM_LOWER, OP_SUB);  // S22 -= L21 L21^H
             continue;
         }
+        if ((err = hipStreamWaitEvent(g.st, e_w, 0)) != hipSuccess) break;        // W = S21^H
+        w_pending = false;
+        if ((err = mm(g, g.MH, g.W, g.LH, kb, t0, t0, N, kb, t0, MM_PU, OP_STORE)) != hipSuccess)
+            break;                                                                 // LH21 = M11 S21^H
         const int t1 = N - t0 < LB ? N : t0 + LB;
         if ((err = hipEventRecord(e_panel, g.st)) != hipSuccess) break;
         if (bulk_pending && (err = hipStreamWaitEvent(g.st, e_bulk, 0)) != hipSuccess) break;
+        if ((err = hipStreamWaitEvent(ga.st, e_panel, 0)) != hipSuccess) break;
+        if ((err = conj_t(ga, g.LH, g.L, kb, t0, t0, N)) != hipSuccess) break;    // L21
+        if (t1 < N && (err = mm(ga, g.LH, g.LH, g.L, t1, N, t1, N, kb, t0, MM_LOWER, OP_SUB)) !=
+                          hipSuccess)
+            break;                                                                 // the rest
+        if ((err = hipEventRecord(e_bulk, ga.st)) != hipSuccess) break;
+        bulk_pending = true;
         if ((err = mm(g, g.LH, g.LH, g.L, t0, N, t0, t1, kb, t0, MM_MASK, OP_SUB)) != hipSuccess)
-            break;                                                                // next column block
-        if (t1 < N) {
-            if ((err = hipStreamWaitEvent(ga.st, e_panel, 0)) != hipSuccess) break;
-            if ((err = mm(ga, g.LH, g.LH, g.L, t1, N, t1, N, kb, t0, MM_LOWER, OP_SUB)) !=
-                hipSuccess)
-                break;                                                            // the rest
-            if ((err = hipEventRecord(e_bulk, ga.st)) != hipSuccess) break;
-            bulk_pending = true;
-        }
+            break;                                                                 // next column block
+        if (t1 < N) err = next_s21h(t0, t1);
     }
+    // join the other streams, also after an error
     if (bulk_pending) {
         const hipError_t e = hipStreamWaitEvent(g.st, e_bulk, 0);
         if (err == hipSuccess) err = e;
     }
-    if (e_panel) (void)hipEventDestroy(e_panel);
-    if (e_bulk) (void)hipEventDestroy(e_bulk);
+    if (w_pending) {
+        const hipError_t e = hipStreamWaitEvent(g.st, e_w, 0);
+        if (err == hipSuccess) err = e;
+    }
+    for (hipEvent_t e : {e_panel, e_bulk, e_next, e_w})
+        if (e) (void)hipEventDestroy(e);
     return err;
 }
 
