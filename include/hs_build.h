@@ -257,7 +257,7 @@ size_t hs_gep_workspace_bytes(int N);
  * Outputs must not overlap the inputs or each other. Returns 0, -i for an
  * invalid argument i (NULL pointer, N < 1, workspace not 16-byte aligned),
  * 2 (workspace too small), or 1 (HIP error).
- * For N > 384 part of the work runs on up to two library-owned streams of the
+ * For N > 384 part of the work runs on up to three library-owned streams of the
  * same device (created on first use, default priority, kept until the process
  * ends), forked from and joined back into `stream` with events: when the call
  * returns, everything it enqueued is ordered before later work on `stream`.
