@@ -32,6 +32,7 @@
 // lower triangle during the factorization), LH (panels L21^H, then V),
 // M = L^{-1} and MH = L^{-H} (zero outside their triangles), W (S21^H,
 // L21 M11), Ht (output).
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -492,14 +493,21 @@ k_gep_init(const double2 *__restrict__ H, const double2 *__restrict__ S, double2
 
 __global__ void k_gep_info_clear(int *info) { *info = 0; }
 
-// D[j][i] = conj(X[i][j]) for i in [i0, i1), j in [j0, j1), through 32 x 32
-// LDS tiles (blockIdx.y: source tile row, blockIdx.x: source tile column)
+// D[j][i] = conj(X[i][j]) for i in [i0, i1), j in [j0, j1) of each job
+// (blockIdx.z), through 32 x 32 LDS tiles (blockIdx.y: source tile row,
+// blockIdx.x: source tile column)
+struct CtJobs {
+    int r[MM_JOBS][4];   // i0, i1, j0, j1
+};
+
 __global__ void __launch_bounds__(256)
-k_gep_conj_t(const double2 *__restrict__ X, double2 *__restrict__ D, int N, int i0, int i1, int j0,
-             int j1) {
+k_gep_conj_t(const double2 *__restrict__ X, double2 *__restrict__ D, int N, const CtJobs jobs) {
     __shared__ double2 tile[32][33];
-    const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+    const int z = blockIdx.z;
+    const int i0 = jobs.r[z][0], i1 = jobs.r[z][1], j0 = jobs.r[z][2], j1 = jobs.r[z][3];
     const int si = i0 + blockIdx.y * 32, sj = j0 + blockIdx.x * 32;
+    if (si >= i1 || sj >= j1) return;   // the grid covers the largest job
+    const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
     for (int r = ty; r < 32; r += 8) {
         const int gr = si + r, gc = sj + tx;
         if (gr < i1 && gc < j1) tile[r][tx] = X[(long long)gr * N + gc];
@@ -586,15 +594,37 @@ hipError_t mm(const Gep &g, const double2 *P, const double2 *Q, double2 *C, int 
     return mm_batch(g, P, Q, C, &r, 1, flags, op);
 }
 
+// Transposes of the rectangles r[0 .. n), up to MM_JOBS per launch.
+hipError_t conj_t_batch(const Gep &g, const double2 *X, double2 *D, const Rect *r, int n) {
+    for (int b = 0; b < n; b += MM_JOBS) {
+        CtJobs j = {};
+        int nj = 0, gx = 0, gy = 0;
+        for (int t = b; t < n && t < b + MM_JOBS; ++t) {
+            if (r[t].i1 <= r[t].i0 || r[t].j1 <= r[t].j0) continue;
+            j.r[nj][0] = r[t].i0;
+            j.r[nj][1] = r[t].i1;
+            j.r[nj][2] = r[t].j0;
+            j.r[nj][3] = r[t].j1;
+            gx = std::max(gx, (r[t].j1 - r[t].j0 + 31) / 32);
+            gy = std::max(gy, (r[t].i1 - r[t].i0 + 31) / 32);
+            ++nj;
+        }
+        if (nj == 0) continue;
+        hipLaunchKernelGGL(k_gep_conj_t, dim3(gx, gy, nj), dim3(256), 0, g.st, X, D, g.N, j);
+        GEP_TRY(hipGetLastError());
+    }
+    return hipSuccess;
+}
+
 hipError_t conj_t(const Gep &g, const double2 *X, double2 *D, int i0, int i1, int j0, int j1) {
-    if (i1 <= i0 || j1 <= j0) return hipSuccess;
-    hipLaunchKernelGGL(k_gep_conj_t, dim3((j1 - j0 + 31) / 32, (i1 - i0 + 31) / 32), dim3(256), 0,
-                       g.st, X, D, g.N, i0, i1, j0, j1);
-    return hipGetLastError();
+    const Rect r = {i0, i1, j0, j1, 0, 0};
+    return conj_t_batch(g, X, D, &r, 1);
 }
 
 // Auxiliary streams per device (0: the factorization's lookahead, 1: work
-// moved off the critical path, 2: the panels' transposes); default priority,
+// moved off the critical path, 2: the panels' transposes; with the caller's
+// stream that is one hardware queue each at the default of four per
+// process); default priority,
 // created once and kept for the life of the process.
 hipStream_t aux_stream(int which) {
     static std::mutex mu;
@@ -726,8 +756,9 @@ hipError_t node_m21(const Gep &g, const std::vector<Node> &nodes) {   // M21 = -
     std::vector<Rect> r;
     for (const Node &n : nodes) r.push_back(Rect{n.m, n.b, n.a, n.m, n.m, n.b});
     GEP_TRY(mm_batch(g, g.MH, g.W, g.M, r.data(), (int)r.size(), MM_PU, OP_NEG));
-    for (const Node &n : nodes) GEP_TRY(conj_t(g, g.M, g.MH, n.m, n.b, n.a, n.m));
-    return hipSuccess;
+    r.clear();
+    for (const Node &n : nodes) r.push_back(Rect{n.m, n.b, n.a, n.m, 0, 0});
+    return conj_t_batch(g, g.M, g.MH, r.data(), (int)r.size());
 }
 
 template <class Keep>
@@ -866,9 +897,8 @@ hipError_t launch_gep(const double2 *H, const double2 *S, int N, double2 *L, dou
     if (err == hipSuccess)
         err = two ? her2k_rows(g, Ht, mt, N)
                   : mm(g, g.LH, g.MH, Ht, 0, N, 0, N, 0, N, MM_QU | MM_LOWER, OP_STORE);
-    if (e_split) (void)hipEventDestroy(e_split);
-    if (e_inv) (void)hipEventDestroy(e_inv);
-    if (e_v) (void)hipEventDestroy(e_v);
+    for (hipEvent_t e : {e_split, e_inv, e_v})
+        if (e) (void)hipEventDestroy(e);
     GEP_TRY(err);
     return launch_mirror1(Ht, N, st);
 }
