@@ -221,9 +221,9 @@ __global__ void __launch_bounds__(MmCfg::NT) k_gep_mm(const MmArgs args) {
 // MFMA fragment loads and the accumulator stores hit distinct banks).
 //   factor, right-looking over 16-column panels P:
 //     wave 0: Cholesky of the diagonal tile in registers (lane r holds row
-//             r; values broadcast with readlane), then its inverse with the
-//             factor read back from LDS;
-//     panel:  L_IP = C_IP inv(L_PP)^H          one tile per wave, MFMA;
+//             r; values broadcast with readlane);
+//     panel:  L_IP = C_IP L_PP^{-H}            by substitution, one thread
+//             per row of the panel;
 //     update: C_IJ -= L_IP L_JP^H, P < J <= I   tiles spread over the waves.
 //   inverse X = L^{-1}, in place: every wave inverts one diagonal tile, then
 //     for block rows I = 1..7: X_IJ = -X_II sum_{J<=K<I} L_IK X_KJ, J < I.
@@ -333,7 +333,6 @@ __global__ void __launch_bounds__(512)
 k_gep_leaf(double2 *__restrict__ L, double2 *__restrict__ M, double2 *__restrict__ MH, int N,
            int kb, int nb, int *__restrict__ info) {
     __shared__ double2 T[LNT * 256];   // 144 KiB
-    __shared__ double2 Ti[256];        // inverse of the current diagonal tile
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -359,7 +358,7 @@ k_gep_leaf(double2 *__restrict__ L, double2 *__restrict__ M, double2 *__restrict
     for (int P = 0; P < LT; ++P) {
         if (w == 0) {
             double2 *D = ltile(T, P, P);
-            double2 a[16], x[16];
+            double2 a[16];
             const int r = lane & 15;
 #pragma unroll
             for (int k = 0; k < 16; ++k) a[k] = D[lsw(r, k)];
@@ -369,22 +368,33 @@ k_gep_leaf(double2 *__restrict__ L, double2 *__restrict__ M, double2 *__restrict
 #pragma unroll
                 for (int k = 0; k < 16; ++k) D[lsw(lane, k)] = a[k];
             }
-            inv16(D, x, lane);   // one wave: its LDS accesses complete in order
-            if (lane < 16) {
-#pragma unroll
-                for (int i = 0; i < 16; ++i) Ti[lsw(i, lane)] = x[i];
-            }
         }
         __syncthreads();
-        // panel: L_IP = C_IP inv(L_PP)^H
-        for (int I = P + 1 + w; I < LT; I += 8) {
-            double2 *C = ltile(T, I, P);
-            Cacc c;
-            acc_zero(c);
-            mma_abh(c, C, Ti, lane);
+        // panel: row r of L_IP solves x L_PP^H = C_IP[r] by substitution,
+        // x_j = (c_j - sum_{k<j} x_k conj(l_jk)) / l_jj, one thread per row
+        if (tid < (LT - 1 - P) * 16) {
+            const double2 *D = ltile(T, P, P);
+            double2 *C = ltile(T, P + 1 + (tid >> 4), P);
+            const int rr = tid & 15;
+            double rd[16];
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                C[lsw(4 * v + (lane >> 4), lane & 15)] = double2{c.re[v], c.im[v]};
+            for (int j = 0; j < 16; ++j) rd[j] = 1.0 / D[lsw(j, j)].x;
+            double2 x[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) x[k] = C[lsw(rr, k)];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                double2 t = x[j];
+#pragma unroll
+                for (int k = 0; k < j; ++k) {   // t -= x_k conj(l_jk)
+                    const double2 l = D[lsw(j, k)];
+                    t.x -= x[k].x * l.x + x[k].y * l.y;
+                    t.y -= x[k].y * l.x - x[k].x * l.y;
+                }
+                x[j] = double2{t.x * rd[j], t.y * rd[j]};
+            }
+#pragma unroll
+            for (int k = 0; k < 16; ++k) C[lsw(rr, k)] = x[k];
         }
         __syncthreads();
         // trailing lower triangle: C_IJ -= L_IP L_JP^H
