@@ -261,6 +261,9 @@ size_t hs_gep_workspace_bytes(int N);
  * same device (created on first use, default priority, kept until the process
  * ends), forked from and joined back into `stream` with events: when the call
  * returns, everything it enqueued is ordered before later work on `stream`.
+ * Calls that overlap on one device share those streams: each still depends
+ * only on its own events (results are unaffected), but their work on the
+ * shared streams runs in the order it was enqueued.
  */
 int hs_gep_reduce(const hs_complex *H, const hs_complex *S, int N,
                   hs_complex *L, hs_complex *Ht, int32_t *info,
