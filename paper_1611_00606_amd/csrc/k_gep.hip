@@ -662,7 +662,7 @@ hipStream_t aux_stream(int which) {
 // write that block); the bulk update and L21 wait for the panel they use;
 // the next S21^H waits for the next column block's update.
 template <class Hook>
-hipError_t factor(const Gep &g, Hook after_leaf) {
+hipError_t factor(const Gep &g, Hook after_panel) {
     const int N = g.N;
     const int np = (N + LB - 1) / LB;
     Gep ga = g, gc = g;
@@ -695,13 +695,13 @@ hipError_t factor(const Gep &g, Hook after_leaf) {
         const int t0 = kb + nb;
         hipLaunchKernelGGL(k_gep_leaf, dim3(1), dim3(512), 0, g.st, g.L, g.M, g.MH, N, kb, nb,
                            g.info);
-        if ((err = hipGetLastError()) != hipSuccess) break;
-        if ((err = after_leaf(t0)) != hipSuccess || t0 >= N) break;
+        if ((err = hipGetLastError()) != hipSuccess || t0 >= N) break;
         if (!ahead) {
             if ((err = conj_t(g, g.L, g.W, t0, N, kb, t0)) != hipSuccess) break;  // W = S21^H
             if ((err = mm(g, g.MH, g.W, g.LH, kb, t0, t0, N, kb, t0, MM_PU, OP_STORE)) !=
                 hipSuccess)
                 break;                                                             // LH21 = M11 S21^H
+            if ((err = after_panel(t0, nullptr)) != hipSuccess) break;
             if ((err = conj_t(g, g.LH, g.L, kb, t0, t0, N)) != hipSuccess) break; // L21
             err = mm(g, g.LH, g.LH, g.L, t0, N, t0, N, kb, t0, MM_LOWER, OP_SUB);  // S22 -= L21 L21^H
             continue;
@@ -710,6 +710,9 @@ hipError_t factor(const Gep &g, Hook after_leaf) {
         w_pending = false;
         if ((err = mm(g, g.MH, g.W, g.LH, kb, t0, t0, N, kb, t0, MM_PU, OP_STORE)) != hipSuccess)
             break;                                                                 // LH21 = M11 S21^H
+        // the hook also gets the lookahead stream's latest event (or null),
+        // which orders that stream's pending work before anything it forks
+        if ((err = after_panel(t0, bulk_pending ? e_bulk : nullptr)) != hipSuccess) break;
         const int t1 = N - t0 < LB ? N : t0 + LB;
         if ((err = hipEventRecord(e_panel, g.st)) != hipSuccess) break;
         if (bulk_pending && (err = hipStreamWaitEvent(g.st, e_bulk, 0)) != hipSuccess) break;
@@ -852,7 +855,7 @@ hipError_t launch_gep(const double2 *H, const double2 *S, int N, double2 *L, dou
     const int np = (N + LB - 1) / LB;
     hipStream_t sb = np >= 8 ? aux_stream(1) : nullptr;
     if (!sb) {
-        GEP_TRY(factor(g, [](int) { return hipSuccess; }));
+        GEP_TRY(factor(g, [](int, hipEvent_t) { return hipSuccess; }));
         GEP_TRY(invert(g, lv, all));
         if (two) {
             GEP_TRY(wh_cols(g, 0, N));
@@ -863,7 +866,8 @@ hipError_t launch_gep(const double2 *H, const double2 *S, int N, double2 *L, dou
         }
         return launch_mirror1(Ht, N, st);
     }
-    // Once the factorization has passed the top split m, the inverse of the
+    // Once the factorization has passed the top split m (the leaf and the
+    // panel product LH21 of the panel ending at m are enqueued), the inverse of the
     // leading block [0, m), the top split's W21 = L21 M11, WH[:, 0:m) and the
     // rows [0, m) of Ht (or V[:, 0:m)) depend on nothing still to come: they run on a second
     // stream, with at most HS_GEP_BG_QUARTERS / 4 of the compute units, beside
@@ -880,10 +884,14 @@ hipError_t launch_gep(const double2 *H, const double2 *S, int N, double2 *L, dou
     bool forked = false;
     const auto left = [mt](const Node &n) { return n.b <= mt; };
     if (err == hipSuccess)
-        err = factor(g, [&](int t0) -> hipError_t {
+        err = factor(g, [&](int t0, hipEvent_t e_ahead) -> hipError_t {
             if (t0 != mt) return hipSuccess;
             GEP_TRY(hipEventRecord(e_split, st));
             GEP_TRY(hipStreamWaitEvent(sb, e_split, 0));
+            // the previous panel's L21 = LH21^H may still read LH columns
+            // >= m - LB on the lookahead stream; V (or WH) overwrites LH's
+            // columns < m below
+            if (e_ahead) GEP_TRY(hipStreamWaitEvent(sb, e_ahead, 0));
             forked = true;
             GEP_TRY(invert(gb, lv, left));
             GEP_TRY(node_w21(gb, {top}));   // L21 and M11 of the top split are final too

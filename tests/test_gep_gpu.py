@@ -192,6 +192,29 @@ def test_deterministic_on_a_side_stream():
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
+def test_overlapping_calls_on_two_streams():
+    """Two reductions enqueued back to back on two streams (sharing the
+    library's streams) give the same bits as each alone; N = 1500 uses the
+    lookahead and the background stream."""
+    from paper_1611_00606_amd import hs_gep_reduce
+    torch = _torch()
+    dev = torch.device("cuda:0")
+    pairs = [_random_pair(1500, seed=s) for s in (21, 22)]
+    alone = [_gep_gpu(H, S) for H, S in pairs]
+    ins = [(torch.from_numpy(H).to(dev), torch.from_numpy(S).to(dev)) for H, S in pairs]
+    outs = [(torch.empty_like(h), torch.empty_like(h), torch.zeros(1, dtype=torch.int32, device=dev))
+            for h, _ in ins]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    for (h, sm), (L, Ht, inf), st in zip(ins, outs, streams):
+        with torch.cuda.stream(st):
+            hs_gep_reduce(h, sm, L, Ht, info=inf, stream=st)
+    torch.cuda.synchronize()
+    for (L, Ht, inf), (La, Hta, ia) in zip(outs, alone):
+        assert int(inf.item()) == ia == 0
+        assert np.array_equal(L.cpu().numpy(), La) and np.array_equal(Ht.cpu().numpy(), Hta)
+
+
 @pytest.mark.parametrize("N,pivot", [(150, 1), (150, 64), (150, 65), (300, 200), (300, 300)])
 def test_failing_pivot_index(N, pivot):
     """S = M D M^H with D_pp < 0: the first pivot that is not > 0 is p
