@@ -39,6 +39,9 @@ INT8_MFMA_PEAK_TOPS = 5000.0    # MI355X dense INT8 matrix peak
 # INT8 MFMA ops per FP64 flop: 15 slice pairs x 2 MFMAs x 2 interleaved
 # products x 2 ops = 120 per complex multiply-add (8 FP64 flops).
 SPLIT_I8_PER_FP64 = 15.0
+# FP64 MFMA flops the 3M form issues per FP64 flop of the reductions: 3 real
+# products per complex multiply-add instead of 4.
+FP64_3M_PER_FP64 = 0.75
 
 
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_reduce_precision_ng8000.md")
@@ -237,20 +240,28 @@ SPLIT_MODES = {
             mode="split_f16 (slices of 8+9+9+9 bits in FP16, 10 slice pairs on FP16 MFMA, FP32 "
                  "accumulation flushed every 64 rows, FP64 recombination)",
             per_fp64=SPLIT_F16_PER_FP64, peak=FP16_MFMA_PEAK_TFLOPS,
-            unit="TFLOP/s (FP16 MFMA flops issued)"),
+            unit="TFLOP/s (FP16 MFMA flops issued)",
+            kernel="slicing + split reduction (phase 2..3)", phase="slice_and_reduce_HS"),
     2: dict(name="split_i8",
             mode="split_i8 (five 7-bit int8 slices, 15 slice pairs on INT8 MFMA, exact INT32 "
                  "accumulation per level, FP64 recombination per segment)",
             per_fp64=SPLIT_I8_PER_FP64, peak=INT8_MFMA_PEAK_TOPS,
-            unit="TOP/s (INT8 MFMA ops issued)"),
+            unit="TOP/s (INT8 MFMA ops issued)",
+            kernel="slicing + split reduction (phase 2..3)", phase="slice_and_reduce_HS"),
+    3: dict(name="fp64_3m",
+            mode="fp64_3m (complex FP64 with 3 real MFMA products per complex product: "
+                 "T1 = pr qr, T2 = pi qi, T3 = (pr - pi)(qr + qi); Re = T1 + T2, Im = T3 - T1 + T2)",
+            per_fp64=FP64_3M_PER_FP64, peak=FP64_MFMA_PEAK_TFLOPS,
+            unit="TFLOP/s (FP64 MFMA flops issued)",
+            kernel="k_reduce, 3M form", phase="reduce_HS"),
 }
 
 
 def split_bench(p, steps: int, warmup: int, fp64_ms: float, hip, mode: int, n_cols: int = 12,
                 atom_kw=None):
-    """Split-precision form on the same workload: time, speedup over the FP64
-    path, and relative Frobenius error of H and of S against the CPU oracle
-    on sampled columns."""
+    """Split-precision (or 3M) form on the same workload: time, speedup over
+    the FP64 path, and relative Frobenius error of H and of S against the CPU
+    oracle on sampled columns."""
     import torch
     import oracle
     from paper_1611_00606_amd import DeviceBuild
@@ -278,9 +289,9 @@ def split_bench(p, steps: int, warmup: int, fp64_ms: float, hip, mode: int, n_co
         "unit": "TFLOP/s (FP64-equivalent)",
         "speedup_vs_fp64": round(fp64_ms / total, 3),
         "phases_ms": {"prep_cholesky": round(float(ph[0]), 4), "atom_products": round(float(ph[1]), 4),
-                      "slice_and_reduce_HS": round(float(ph[2]), 4), "mirror": round(float(ph[3]), 4)},
+                      m["phase"]: round(float(ph[2]), 4), "mirror": round(float(ph[3]), 4)},
         "roofline": {
-            "kernel": "slicing + split reduction (phase 2..3)",
+            "kernel": m["kernel"],
             "bound": "mfma",
             "achieved": round(issued, 2),
             "peak": m["peak"],
@@ -398,7 +409,7 @@ def serving_bench(seed: int, n_slots: int = 4, arena_gb: float = 24.0, n_sets: i
     out["latency_samples"] = len(reqs) * streams
     out["offered_rate_per_s"] = [round(x, 3) for x in offered]
     out.update({
-        "mode": {0: "fp64", 1: "split_f16", 2: "split_i8"}[mode],
+        "mode": {0: "fp64", 1: "split_f16", 2: "split_i8", 3: "fp64_3m"}[mode],
         "workload": "64 requests, N_A=64 atoms, N_L=64, N_G uniform in [1500, 9000], Poisson arrivals",
         "arrival_rate_per_s": rate,   # nominal Poisson rate; offered_rate_per_s is realized
         "load": load,
@@ -487,9 +498,10 @@ def main():
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving-form measurement (k-point builds/s, p50/p99)")
     ap.add_argument("--no-split", action="store_true",
-                    help="skip the split-precision measurement")
-    ap.add_argument("--split-modes", default="1,2",
-                    help="split modes to measure (1 = HS_SPLIT_F16, 2 = HS_SPLIT_I8)")
+                    help="skip the split-precision and 3M measurements")
+    ap.add_argument("--split-modes", default="1,2,3",
+                    help="alternative reduction modes to measure (1 = HS_SPLIT_F16, "
+                         "2 = HS_SPLIT_I8, 3 = HS_FP64_3M)")
     ap.add_argument("--per-atom", choices=["batched", "separate"], default="batched",
                     help="per-atom stage of the timed builds: the batched persistent launch with "
                          "autotuned tile shapes, or separate preparation and product launches")
@@ -621,7 +633,7 @@ def main():
     torch.cuda.empty_cache()
     out["hs_build_sync_wall_ms"] = sync_build_wall_ms(p)
     if not args.no_split:
-        print("bench: split precision", file=sys.stderr, flush=True)
+        print("bench: split precision and 3M", file=sys.stderr, flush=True)
         hip = HipEvents()
         for mode in [int(m) for m in args.split_modes.split(",") if m]:
             out[SPLIT_MODES[mode]["name"]] = split_bench(p, max(3, args.steps // 2), 1, ms_step,
@@ -641,6 +653,7 @@ def main():
         if not args.no_split:
             out["serving_split_f16"] = serving_bench(args.seed, mode=1)
             out["serving_split_i8"] = serving_bench(args.seed, mode=2)
+            out["serving_fp64_3m"] = serving_bench(args.seed, mode=3)
     print(json.dumps(out), flush=True)
 
 

@@ -98,11 +98,22 @@ enum {
  *                 accumulation per level, recombined in binary64 once per
  *                 contraction segment. Error about 2^-35 of the operand
  *                 column maxima per product term (same order as
- *                 HS_SPLIT_F16). Inputs must be finite. */
+ *                 HS_SPLIT_F16). Inputs must be finite.
+ *   HS_FP64_3M    complex binary64 MFMA with 3 real products per complex
+ *                 product instead of 4 (the 3M or Gauss form: for conj(p) q,
+ *                 T1 = pr qr, T2 = pi qi, T3 = (pr - pi)(qr + qi) summed
+ *                 over the contraction, Re = T1 + T2, Im = T3 - T1 + T2).
+ *                 Three quarters of the matrix-core work of HS_FP64; the
+ *                 real parts are the same sums, the imaginary parts' error
+ *                 bound grows from u (|pr||qi| + |pi||qr|) to
+ *                 u (|pr - pi||qr + qi| + |pr||qr| + |pi||qi|) per term
+ *                 (u = 2^-53, times the usual contraction-length factor).
+ *                 Same workspace as HS_FP64. */
 typedef enum {
     HS_FP64 = 0,
     HS_SPLIT_F16 = 1,
-    HS_SPLIT_I8 = 2
+    HS_SPLIT_I8 = 2,
+    HS_FP64_3M = 3
 } hs_mode;
 
 /* Tile shapes of the batched per-atom stage (see hs_options.batch): shape id

@@ -257,7 +257,8 @@ hipError_t enqueue_kpoint(const AtomPlan &p, const AtomBufs &ab, int n_g, int mo
         e = mode == HS_SPLIT_I8 ? launch_split8_reduce(K, n_g, hseg, sseg, H, S, st)
                                 : launch_split_reduce(K, n_g, hseg, sseg, H, S, st);
     } else {
-        e = launch_reduce(p.K, n_g, A, B, kb.Z, kb.W, ab.sel, ab.d, H, S, st);
+        e = launch_reduce(p.K, n_g, A, B, kb.Z, kb.W, ab.sel, ab.d, H, S, st,
+                          mode == HS_FP64_3M);
     }
     if (e != hipSuccess) return e;
     if ((e = mark(3)) != hipSuccess) return e;

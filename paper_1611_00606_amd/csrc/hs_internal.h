@@ -45,10 +45,11 @@ hipError_t launch_atom(const Atoms &at, int n_g, const double2 *A, const double2
                        double2 *Z, double2 *W, hipStream_t st);
 
 // Large reductions (Alg. 1's zher2k, zherk pair of S, failure-branch zgemm
-// and HPD zherk) into the lower triangles of H and S (complex FP64 MFMA).
+// and HPD zherk) into the lower triangles of H and S (complex FP64 MFMA;
+// g3: 3 real products per complex product instead of 4).
 hipError_t launch_reduce(int K, int n_g, const double2 *A, const double2 *B,
                          const double2 *Z, const double2 *W, const int *sel,
-                         const double *d, double2 *H, double2 *S, hipStream_t st);
+                         const double *d, double2 *H, double2 *S, hipStream_t st, bool g3);
 
 // Error bookkeeping shared by the C entry points (thread-local message).
 void set_error(const std::string &msg);
@@ -56,8 +57,8 @@ const std::string &last_error();
 int hip_fail(hipError_t e, const char *where);   // records the message, returns HS_ERR_HIP
 int check_device();                              // HS_OK on gfx950, else an error status
 int num_cus();                                   // compute units of the current device
-inline bool valid_mode(int mode) {   // HS_FP64, HS_SPLIT_F16, HS_SPLIT_I8
-    return mode == HS_FP64 || mode == HS_SPLIT_F16 || mode == HS_SPLIT_I8;
+inline bool valid_mode(int mode) {   // HS_FP64, HS_SPLIT_F16, HS_SPLIT_I8, HS_FP64_3M
+    return mode == HS_FP64 || mode == HS_SPLIT_F16 || mode == HS_SPLIT_I8 || mode == HS_FP64_3M;
 }
 inline bool split_mode(int mode) { return mode == HS_SPLIT_F16 || mode == HS_SPLIT_I8; }
 

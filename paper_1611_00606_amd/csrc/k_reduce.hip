@@ -16,6 +16,10 @@
 // banded tile order, and the blocks resident on one XCD share the column
 // panels they read through that XCD's L2.
 //
+// With G3 every complex product takes 3 real MFMA products instead of 4 (the
+// 3M form, see zmfma_direct.h): three quarters of the matrix-core work, a
+// slightly larger rounding bound on the imaginary parts.
+//
 // k_mirror (launched separately, also after the split-precision reduction)
 // completes both outputs: upper = conj(lower), Im(diag) = 0.
 #include "hs_internal.h"
@@ -99,6 +103,7 @@ __device__ __forceinline__ void band_tile(int t, int nt, int &ti, int &tj) {
     }
 }
 
+template <bool G3>
 __global__ void __launch_bounds__(RedCfg::NT)
 k_reduce(RedArgs args) {
     using C = RedCfg;
@@ -136,8 +141,9 @@ k_reduce(RedArgs args) {
         t.sel = args.sel;      // [3K]: 0 on the first two segments
         t.qscale = nullptr;
 #if HS_RED_DIRECT
-        ztile_direct<C>(t, m0, args.n_g, n0, args.n_g, acc, lds);
+        ztile_direct<C, 3, true, false, G3>(t, m0, args.n_g, n0, args.n_g, acc, lds);
 #else
+        static_assert(!G3, "the 3M form needs the direct loader");
         ztile_run<C>(t, m0, args.n_g, n0, args.n_g, acc, lds);
 #endif
     } else {
@@ -154,7 +160,7 @@ k_reduce(RedArgs args) {
         t.sel = nullptr;
         t.qscale = args.d;     // [2K]: 1 on A's rows, |u|^2 on B's rows
 #if HS_RED_DIRECT
-        ztile_direct<C>(t, m0, args.n_g, n0, args.n_g, acc, lds);
+        ztile_direct<C, 2, false, true, G3>(t, m0, args.n_g, n0, args.n_g, acc, lds);
 #else
         ztile_run<C>(t, m0, args.n_g, n0, args.n_g, acc, lds);
 #endif
@@ -209,7 +215,7 @@ k_mirror(double2 *H, double2 *S, int n_g) {
 
 hipError_t launch_reduce(int K, int n_g, const double2 *A, const double2 *B,
                          const double2 *Z, const double2 *W, const int *sel,
-                         const double *d, double2 *H, double2 *S, hipStream_t st) {
+                         const double *d, double2 *H, double2 *S, hipStream_t st, bool g3) {
     using C = RedCfg;
     RedArgs args;
     args.A = A;
@@ -225,7 +231,10 @@ hipError_t launch_reduce(int K, int n_g, const double2 *A, const double2 *B,
     args.nt = (n_g + C::BM - 1) / C::BM;
     args.ntri = args.nt * (args.nt + 1) / 2;
     args.ntri8 = (args.ntri + 7) / 8 * 8;
-    hipLaunchKernelGGL(k_reduce, dim3(2 * args.ntri8), dim3(C::NT), 0, st, args);
+    if (g3)
+        hipLaunchKernelGGL(k_reduce<true>, dim3(2 * args.ntri8), dim3(C::NT), 0, st, args);
+    else
+        hipLaunchKernelGGL(k_reduce<false>, dim3(2 * args.ntri8), dim3(C::NT), 0, st, args);
     return hipGetLastError();
 }
 

@@ -18,13 +18,24 @@
 // loads while the current one is multiplied; the buffers are handed to the
 // stage body as distinct (restrict) pointers, without which the compiler
 // waits for the loads before the stage's LDS reads.
+//
+// G3: the complex product in 3 real products instead of 4 (the 3M or Gauss
+// form): per contraction row, with p = pr + i pi and q = qr + i qi,
+//   T1 += pr qr,   T2 += pi qi,   T3 += (pr - pi)(qr + qi)
+// and at the end Re = T1 + T2, Im = T3 - T1 + T2, which is conj(p) q summed.
+// T1 and T2 live in acc.re and acc.im until the final fold. The real part is
+// the same sum as in the 4-product form; the imaginary part's rounding error
+// is bounded by the unit roundoff times |pr - pi||qr + qi| + |pr||qr| +
+// |pi||qi| (summed over the contraction) instead of |pr||qi| + |pi||qr|.
+// Three accumulator sets of a 64x32 wave tile take 192 of the 256 registers
+// a wave has at two waves per SIMD, so the fragments are not double-buffered.
 #pragma once
 
 #include "zmfma_tile.h"
 
 namespace hs {
 
-template <class C, int NSEG, bool SEL, bool SCALE>
+template <class C, int NSEG, bool SEL, bool SCALE, bool G3 = false>
 __device__ __forceinline__ void ztile_direct(const Segs<NSEG, SEL, SCALE> &t, int m0, int mlim,
                                              int n0, int nlim, Acc<C> &acc, double2 *lds) {
     static_assert(C::BK == 16 && C::NT == 512, "8 waves load rows w and w + 8 of a 16-row stage");
@@ -43,6 +54,13 @@ __device__ __forceinline__ void ztile_direct(const Segs<NSEG, SEL, SCALE> &t, in
             acc.re[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
             acc.im[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
         }
+    v4d t3[G3 ? C::TM : 1][G3 ? C::TN : 1];
+    if constexpr (G3) {
+#pragma unroll
+        for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+            for (int j = 0; j < C::TN; ++j) t3[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    }
 
     const int ktot = t.nseg * t.len;
     const int nst = (ktot + C::BK - 1) / C::BK;
@@ -126,6 +144,29 @@ __device__ __forceinline__ void ztile_direct(const Segs<NSEG, SEL, SCALE> &t, in
         }
     };
     auto mma = [&](const double2 (&a)[C::TM], const double2 (&b)[C::TN]) __attribute__((always_inline)) {
+        if constexpr (G3) {
+            double sb[C::TN];
+#pragma unroll
+            for (int j = 0; j < C::TN; ++j) sb[j] = b[j].x + b[j].y;
+#pragma unroll
+            for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+                for (int j = 0; j < C::TN; ++j)
+                    acc.re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].x, acc.re[i][j], 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+                for (int j = 0; j < C::TN; ++j)
+                    acc.im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, b[j].y, acc.im[i][j], 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < C::TM; ++i) {
+                const double sa = a[i].x - a[i].y;
+#pragma unroll
+                for (int j = 0; j < C::TN; ++j)
+                    t3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa, sb[j], t3[i][j], 0, 0, 0);
+            }
+            return;
+        }
         double nbr[C::TN];
 #pragma unroll
         for (int j = 0; j < C::TN; ++j) nbr[j] = -b[j].x;
@@ -152,7 +193,7 @@ __device__ __forceinline__ void ztile_direct(const Segs<NSEG, SEL, SCALE> &t, in
     };
     auto interleave = [&]() __attribute__((always_inline)) {
         constexpr int NR = C::TM + C::TN;
-        constexpr int NM = 4 * C::TM * C::TN;
+        constexpr int NM = (G3 ? 3 : 4) * C::TM * C::TN;
         constexpr int PER = NM / (NR + 1);
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
@@ -163,6 +204,15 @@ __device__ __forceinline__ void ztile_direct(const Segs<NSEG, SEL, SCALE> &t, in
     };
     static_assert((C::BK / 4) % 2 == 0, "K steps per stage must be even");
     auto compute = [&](const double2 *lp, const double2 *lq) __attribute__((always_inline)) {
+        if constexpr (G3) {
+#pragma unroll
+            for (int k4 = 0; k4 < C::BK / 4; ++k4) {
+                double2 fa[C::TM], fb[C::TN];
+                ldfrag(lp, lq, k4, fa, fb);
+                mma(fa, fb);   // no interleave hints: the free schedule is faster here
+            }
+            return;
+        }
         double2 fa0[C::TM], fb0[C::TN], fa1[C::TM], fb1[C::TN];
         ldfrag(lp, lq, 0, fa0, fb0);
 #pragma unroll
@@ -197,6 +247,16 @@ __device__ __forceinline__ void ztile_direct(const Segs<NSEG, SEL, SCALE> &t, in
         }
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
+    }
+    if constexpr (G3) {
+#pragma unroll
+        for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+            for (int j = 0; j < C::TN; ++j) {
+                const v4d t1 = acc.re[i][j], t2 = acc.im[i][j];
+                acc.re[i][j] = t1 + t2;
+                acc.im[i][j] = (t3[i][j] - t1) + t2;
+            }
     }
 }
 

@@ -90,9 +90,10 @@ def test_null_outputs():
 def test_build_ex_option_checks():
     lib = P.load_library()
     assert lib.hs_build_ex(*[FAKE] * 6, 2, 4, 8, FAKE, FAKE, None) == -12
-    opt = Bd.hs_options()
-    opt.mode = 3
-    assert lib.hs_build_ex(*[FAKE] * 6, 2, 4, 8, FAKE, FAKE, ctypes.byref(opt)) == -12
+    for bad in (4, -1):
+        opt = Bd.hs_options()
+        opt.mode = bad
+        assert lib.hs_build_ex(*[FAKE] * 6, 2, 4, 8, FAKE, FAKE, ctypes.byref(opt)) == -12
     nl = np.array([4, 200], np.int32)
     opt = Bd.hs_options()
     opt.nl_per_atom = nl.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
@@ -156,7 +157,10 @@ def test_split_mode_workspace():
     groups8 = (K + 31) // 32 * 4
     assert i8 >= fp64 + 6 * 5 * groups8 * 1000 * 16
     assert i8 < split   # 5 bytes per real value against 8
-    assert P.hs_workspace_bytes(10, None, 49, 1000, 3) == 0
+    # the 3M form changes only the arithmetic of the reductions
+    assert P.hs_workspace_bytes(10, None, 49, 1000, P.HS_FP64_3M) == fp64
+    assert P.hs_workspace_bytes(10, None, 49, 1000, 4) == 0
+    assert P.hs_workspace_bytes(10, None, 49, 1000, -1) == 0
 
 
 def test_tile_configs():

@@ -1,0 +1,159 @@
+"""The 3M form of the reductions (HS_FP64_3M) against the CPU oracle.
+
+With 3 real products per complex product, Re = T1 + T2 is the same sum as in
+the 4-product form and Im = T3 - T1 + T2 carries a rounding bound of
+u (|pr - pi||qr + qi| + |pr||qr| + |pi||qi|) per term instead of
+u (|pr||qi| + |pi||qr|): at most about 2 + sqrt(2) times larger for a
+balanced term, so the relative Frobenius error of H and S stays far inside the
+1e-12 the FP64 parity tests use (random-sign rounding grows like sqrt(K) u,
+about 1e-14 at K = 8100). The tests check that bar against the oracle, that
+the mode really takes another kernel (results differ from HS_FP64 in the
+last bits), exact Hermitian symmetry and the branch flags, and that the
+serving context computes the same bits as the one-shot build.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from hs_inputs import make_config, make_problem, cn
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _build(p, mode):
+    from paper_1611_00606_amd import DeviceBuild
+    torch = _torch()
+    print(f"case N_A={p.N_A} nl={sorted(set(p.nl.tolist()))} N_G={p.N_G} failing={p.failing} "
+          f"planted={p.planted} mode={mode}", flush=True)
+    r = DeviceBuild.from_problem(p, mode=mode)
+    r.run()
+    torch.cuda.synchronize()
+    return r
+
+
+def _rel(x, y):
+    return np.linalg.norm(x - y) / np.linalg.norm(y)
+
+
+def _expected_info(p):
+    info = np.zeros(p.N_A, np.int32)
+    for a in p.failing:
+        info[a] = 1
+    for a, piv in p.planted.items():
+        info[a] = piv
+    return info
+
+
+CASES = {
+    "plain_tiny": lambda: make_config("plain_tiny", seed=0),
+    "one_element": lambda: make_problem(1, 1, 1, seed=2),
+    "ng_tile_plus_one": lambda: make_problem(2, 3, 129, seed=3),
+    "ng_below_block": lambda: make_problem(3, 5, 7, seed=4, fail_atoms=[2]),
+    "nl_max_128": lambda: make_problem(2, 128, 200, seed=5, planted={1: 100}),
+    "all_failing": lambda: make_problem(3, 9, 300, seed=7, fail_atoms=[0, 1, 2]),
+    "mixed_nl": lambda: make_problem(6, [16, 49, 81, 121, 1, 128], 700, seed=8,
+                                     fail_atoms=[2], planted={3: 50}),
+    "long_contraction": lambda: make_problem(260, 128, 97, seed=10, fail_atoms=[5, 200]),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_full_parity(name):
+    from paper_1611_00606_amd import HS_FP64_3M
+    p = CASES[name]()
+    r = _build(p, HS_FP64_3M)
+    H, S, info = r.results()
+    Hr = O.hamiltonian(p.A, p.B, p.T_AA, p.T_AB, p.T_BB, p.nl)
+    Sr = O.overlap(p.A, p.B, p.U, p.nl)
+    eh, es = _rel(H, Hr), _rel(S, Sr)
+    print(f"  rel err H {eh:.2e} S {es:.2e}", flush=True)
+    assert eh <= TOL and es <= TOL, (eh, es)
+    assert np.array_equal(H, H.conj().T) and np.array_equal(S, S.conj().T)
+    assert np.all(H.diagonal().imag == 0) and np.all(S.diagonal().imag == 0)
+    assert np.array_equal(info, _expected_info(p))
+
+
+def test_differs_from_four_product_form_in_the_last_bits():
+    from paper_1611_00606_amd import HS_FP64, HS_FP64_3M
+    p = make_problem(4, [16, 49, 81, 9], 300, seed=31, fail_atoms=[3])
+    H4, S4, i4 = _build(p, HS_FP64).results()
+    H3, S3, i3 = _build(p, HS_FP64_3M).results()
+    assert np.array_equal(i4, i3)
+    # another kernel ran: the imaginary parts are other sums
+    assert not np.array_equal(H3.imag, H4.imag) and not np.array_equal(S3.imag, S4.imag)
+    # by rounding only
+    assert _rel(H3, H4) <= TOL and _rel(S3, S4) <= TOL
+    # the real parts are the same sums in another order
+    assert _rel(H3.real, H4.real) <= TOL and _rel(S3.real, S4.real) <= TOL
+
+
+def test_deterministic():
+    from paper_1611_00606_amd import HS_FP64_3M
+    p = make_problem(3, [49, 81, 16], 640, seed=32, fail_atoms=[1])
+    H1, S1, _ = _build(p, HS_FP64_3M).results()
+    H2, S2, _ = _build(p, HS_FP64_3M).results()
+    assert np.array_equal(H1, H2) and np.array_equal(S1, S2)
+
+
+def test_full_size_sampled():
+    """The benchmark's workload (N_G = 8000, K = 8100): sampled columns and
+    bilinear probes against the oracle."""
+    from paper_1611_00606_amd import HS_FP64_3M
+    torch = _torch()
+    p = make_config("precision", seed=0)
+    r = _build(p, HS_FP64_3M)
+    rng = np.random.default_rng(1)
+    cols = sorted(set([0, 1, 127, 128, p.N_G // 2, p.N_G - 1] + rng.integers(0, p.N_G, 6).tolist()))
+    idx = torch.as_tensor(np.asarray(cols), device=r.H.device)
+    Hc = r.H.index_select(1, idx).cpu().numpy()
+    Sc = r.S.index_select(1, idx).cpu().numpy()
+    Hr = O.hamiltonian_columns(p.A, p.B, p.T_AA, p.T_AB, p.T_BB, p.nl, cols)
+    Sr = O.overlap_columns(p.A, p.B, p.U, p.nl, cols)
+    for j, g in enumerate(cols):
+        eh = np.linalg.norm(Hc[:, j] - Hr[:, j]) / np.linalg.norm(Hr[:, j])
+        es = np.linalg.norm(Sc[:, j] - Sr[:, j]) / np.linalg.norm(Sr[:, j])
+        assert eh <= TOL and es <= TOL, (g, eh, es)
+    Hd = r.H.cpu().numpy()
+    Sd = r.S.cpu().numpy()
+    assert np.array_equal(Hd, Hd.conj().T) and np.array_equal(Sd, Sd.conj().T)
+    fro_h, fro_s = np.linalg.norm(Hd), np.linalg.norm(Sd)
+    prng = np.random.default_rng(0)
+    for _ in range(2):
+        x, y = cn(prng, (p.N_G,)), cn(prng, (p.N_G,))
+        h, s = O.bilinear(p.A, p.B, p.T_AA, p.T_AB, p.T_BB, p.U, p.nl, x, y)
+        nx, ny = np.linalg.norm(x), np.linalg.norm(y)
+        assert abs(y.conj() @ (Hd @ x) - h) <= TOL * fro_h * nx * ny
+        assert abs(y.conj() @ (Sd @ x) - s) <= TOL * fro_s * nx * ny
+    assert np.array_equal(r.info.cpu().numpy(), _expected_info(p))
+
+
+def test_context_build_equals_one_shot():
+    from paper_1611_00606_amd import HS_FP64_3M
+    from paper_1611_00606_amd.serving import Context
+    torch = _torch()
+    atoms = make_problem(4, [16, 49, 25, 64], 1, seed=33, fail_atoms=[2])
+    n_g = 513
+    q = make_problem(atoms.N_A, atoms.nl, n_g, seed=34)
+    q.T_AA, q.T_AB, q.T_BB, q.U = atoms.T_AA, atoms.T_AB, atoms.T_BB, atoms.U
+    H1, S1, _ = _build(q, HS_FP64_3M).results()
+    ctx = Context(atoms.T_AA, atoms.T_AB, atoms.T_BB, atoms.U, atoms.nl)
+    try:
+        dev = torch.device("cuda:0")
+        A = torch.from_numpy(q.A).to(dev)
+        Bm = torch.from_numpy(q.B).to(dev)
+        H = torch.empty((n_g, n_g), dtype=torch.complex128, device=dev)
+        S = torch.empty_like(H)
+        ws = torch.empty(ctx.workspace_bytes(n_g, HS_FP64_3M), dtype=torch.uint8, device=dev)
+        ctx.build(A, Bm, n_g, H, S, ws, mode=HS_FP64_3M)
+        torch.cuda.synchronize()
+        assert np.array_equal(H.cpu().numpy(), H1) and np.array_equal(S.cpu().numpy(), S1)
+    finally:
+        ctx.close()
