@@ -425,9 +425,9 @@ def serving_bench(seed: int, n_slots: int = 4, arena_gb: float = 24.0, n_sets: i
 def gep_bench(run, steps: int, hip):
     """Reduction of the generalized eigenproblem (S = L L^H, Ht = L^-1 H L^-H)
     applied to the H and S this build produced, timed with HIP events on the
-    launch stream."""
+    launch stream; then the same with the products in the 3M form."""
     import torch
-    from paper_1611_00606_amd import hs_gep_reduce, hs_gep_workspace_bytes
+    from paper_1611_00606_amd import HS_FP64, HS_FP64_3M, hs_gep_reduce, hs_gep_workspace_bytes
     N = int(run.H.shape[0])
     dev = run.H.device
     L = torch.empty_like(run.H)
@@ -435,20 +435,25 @@ def gep_bench(run, steps: int, hip):
     info = torch.zeros(1, dtype=torch.int32, device=dev)
     ws = torch.empty(hs_gep_workspace_bytes(N), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
-    hs_gep_reduce(run.H, run.S, L, Ht, info=info, workspace=ws, stream=stream)
-    torch.cuda.synchronize()
     rt = hip.rt
     rt.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
-    ms = []
-    for _ in range(steps):
-        e0, e1 = hip.create(2)
-        assert rt.hipEventRecord(ctypes.c_void_p(e0), ctypes.c_void_p(stream.cuda_stream)) == 0
-        hs_gep_reduce(run.H, run.S, L, Ht, info=info, workspace=ws, stream=stream)
-        assert rt.hipEventRecord(ctypes.c_void_p(e1), ctypes.c_void_p(stream.cuda_stream)) == 0
+
+    def timed(mode):
+        hs_gep_reduce(run.H, run.S, L, Ht, info=info, workspace=ws, stream=stream, mode=mode)
         torch.cuda.synchronize()
-        ms.append(hip.elapsed_ms(e0, e1))
-        hip.destroy([e0, e1])
-    res = float(torch.linalg.matrix_norm(L @ L.conj().T - run.S) / torch.linalg.matrix_norm(run.S))
+        ms = []
+        for _ in range(steps):
+            e0, e1 = hip.create(2)
+            assert rt.hipEventRecord(ctypes.c_void_p(e0), ctypes.c_void_p(stream.cuda_stream)) == 0
+            hs_gep_reduce(run.H, run.S, L, Ht, info=info, workspace=ws, stream=stream, mode=mode)
+            assert rt.hipEventRecord(ctypes.c_void_p(e1), ctypes.c_void_p(stream.cuda_stream)) == 0
+            torch.cuda.synchronize()
+            ms.append(hip.elapsed_ms(e0, e1))
+            hip.destroy([e0, e1])
+        res = float(torch.linalg.matrix_norm(L @ L.conj().T - run.S) / torch.linalg.matrix_norm(run.S))
+        return ms, res
+
+    ms, res = timed(HS_FP64)
     med = float(np.median(ms))
     f_def = 28.0 / 3.0 * N ** 3    # Cholesky + two triangular solves with N columns
     # executed: factor and inverse 8/3 N^3, then V = H L^-H and Ht (16/3 N^3), or from
@@ -464,6 +469,16 @@ def gep_bench(run, steps: int, hip):
         "residual_S_LLH": res,
         "flop_counts": "by_definition 28/3 N^3 (Cholesky 4/3 N^3 + two solves 4 N^3 each); "
                        "executed 20/3 N^3 from N = 4096 (8 N^3 below)",
+    }
+    ms3, res3 = timed(HS_FP64_3M)
+    med3 = float(np.median(ms3))
+    out["fp64_3m"] = {
+        "mode": "products on the tiles in the 3M form (3 real MFMA products per complex product)",
+        "info": int(info.item()),
+        "ms_median": round(med3, 3), "ms_min": round(float(min(ms3)), 3),
+        "tflops_by_definition": round(f_def / (med3 * 1e-3) / 1e12, 2),
+        "speedup_vs_fp64": round(med / med3, 3),
+        "residual_S_LLH": res3,
     }
     del L, Ht, ws
     torch.cuda.empty_cache()

@@ -280,6 +280,18 @@ int hs_gep_reduce(const hs_complex *H, const hs_complex *S, int N,
                   hs_complex *L, hs_complex *Ht, int32_t *info,
                   void *workspace, size_t workspace_bytes, void *stream);
 
+/*
+ * hs_gep_reduce_ex - hs_gep_reduce with the arithmetic of its large products
+ * chosen by 10 mode: HS_FP64 (as hs_gep_reduce) or HS_FP64_3M (3 real MFMA
+ * products per complex product in every product on the tiles; the 128x128
+ * diagonal blocks are still factored and inverted in the 4-product form;
+ * error bound of the imaginary parts as described at hs_mode). Any other
+ * mode returns -10; arguments 1..9 and the other statuses as hs_gep_reduce.
+ */
+int hs_gep_reduce_ex(const hs_complex *H, const hs_complex *S, int N,
+                     hs_complex *L, hs_complex *Ht, int32_t *info,
+                     void *workspace, size_t workspace_bytes, void *stream, int mode);
+
 /* ------------------------------------------------------------------------
  * Resident context: one atom set, many k-points.
  *

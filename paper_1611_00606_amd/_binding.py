@@ -149,6 +149,8 @@ def load_library() -> ctypes.CDLL:
     lib.hs_gep_workspace_bytes.restype = sz
     lib.hs_gep_reduce.argtypes = [vp, vp, i32, vp, vp, vp, vp, sz, vp]
     lib.hs_gep_reduce.restype = i32
+    lib.hs_gep_reduce_ex.argtypes = [vp, vp, i32, vp, vp, vp, vp, sz, vp, i32]
+    lib.hs_gep_reduce_ex.restype = i32
     _lib = lib
     return lib
 
@@ -407,10 +409,12 @@ def hs_gep_workspace_bytes(N) -> int:
     return int(load_library().hs_gep_workspace_bytes(int(N)))
 
 
-def hs_gep_reduce(H, S, L, Ht, *, info=None, workspace=None, stream=None, check=True) -> int:
+def hs_gep_reduce(H, S, L, Ht, *, info=None, workspace=None, stream=None, check=True,
+                  mode: int = HS_FP64) -> int:
     """S = L L^H, Ht = L^-1 H L^-H on `stream` (asynchronous). H, S, L, Ht:
     complex128 device tensors [N][N]; info: int32 device tensor [1] or None;
-    workspace: uint8 device tensor (allocated here when None)."""
+    workspace: uint8 device tensor (allocated here when None); mode: HS_FP64
+    (hs_gep_reduce) or HS_FP64_3M (hs_gep_reduce_ex)."""
     import torch
     _check_c128(H, S, L, Ht)
     N = int(H.shape[0])
@@ -421,6 +425,11 @@ def hs_gep_reduce(H, S, L, Ht, *, info=None, workspace=None, stream=None, check=
         workspace = torch.empty(hs_gep_workspace_bytes(N), dtype=torch.uint8, device=H.device)
     if info is not None and info.dtype != torch.int32:
         raise ValueError("info must be int32")
-    rc = load_library().hs_gep_reduce(_ptr(H), _ptr(S), N, _ptr(L), _ptr(Ht), _ptr(info),
-                                      _ptr(workspace), workspace.numel(), _stream_handle(stream))
+    lib = load_library()
+    args = (_ptr(H), _ptr(S), N, _ptr(L), _ptr(Ht), _ptr(info), _ptr(workspace),
+            workspace.numel(), _stream_handle(stream))
+    if mode == HS_FP64:
+        rc = lib.hs_gep_reduce(*args)
+    else:
+        rc = lib.hs_gep_reduce_ex(*args, int(mode))
     return _raise(rc, check)

@@ -387,17 +387,25 @@ size_t hs_gep_workspace_bytes(int N) { return N < 1 ? 0 : hs::gep_workspace_byte
 
 int hs_gep_reduce(const hs_complex *H, const hs_complex *S, int N, hs_complex *L, hs_complex *Ht,
                   int32_t *info, void *workspace, size_t workspace_bytes, void *stream) {
+    return hs_gep_reduce_ex(H, S, N, L, Ht, info, workspace, workspace_bytes, stream, HS_FP64);
+}
+
+int hs_gep_reduce_ex(const hs_complex *H, const hs_complex *S, int N, hs_complex *L,
+                     hs_complex *Ht, int32_t *info, void *workspace, size_t workspace_bytes,
+                     void *stream, int mode) {
     if (!H) return -1;
     if (!S) return -2;
     if (N < 1) return -3;
     if (!L) return -4;
     if (!Ht) return -5;
     if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 16) return -7;
+    if (mode != HS_FP64 && mode != HS_FP64_3M) return -10;
     int rc = hs::check_device();
     if (rc != HS_OK) return rc;
     if (workspace_bytes < hs::gep_workspace_bytes(N)) return HS_ERR_WORKSPACE;
     hipError_t e = hs::launch_gep(c2(H), c2(S), N, c2(L), c2(Ht), info,
-                                  static_cast<char *>(workspace), static_cast<hipStream_t>(stream));
+                                  static_cast<char *>(workspace), static_cast<hipStream_t>(stream),
+                                  mode == HS_FP64_3M);
     return e == hipSuccess ? HS_OK : hs::hip_fail(e, "hs_gep_reduce launch");
 }
 

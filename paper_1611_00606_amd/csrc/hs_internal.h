@@ -99,10 +99,11 @@ hipError_t launch_mirror(double2 *H, double2 *S, int n_g, hipStream_t st);
 hipError_t launch_mirror1(double2 *M, int n, hipStream_t st);
 
 // Generalized eigenproblem reduction (k_gep.hip): S = L L^H, Ht = L^-1 H L^-H.
-// info: device int or NULL (a workspace slot is used then).
+// info: device int or NULL (a workspace slot is used then); g3: the large
+// products in the 3M form.
 size_t gep_workspace_bytes(int N);
 hipError_t launch_gep(const double2 *H, const double2 *S, int N, double2 *L, double2 *Ht,
-                      int *info, char *ws, hipStream_t st);
+                      int *info, char *ws, hipStream_t st, bool g3);
 
 // ---------------------------------------------------------------------------
 // Host-side plan of one atom set and the enqueue steps shared by the one-shot

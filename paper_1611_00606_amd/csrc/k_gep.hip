@@ -86,8 +86,9 @@ struct MmArgs {
 
 // C[i][j] (op)= sum_k conj(P[k][i]) Q[k][j] over each job's rectangle, in
 // absolute indices; the triangular flags trim each tile's contraction range
-// to the rows where both operands can be nonzero.
-template <int NSEG>
+// to the rows where both operands can be nonzero. G3: 3 real products per
+// complex product (the 3M form of the tile engine).
+template <int NSEG, bool G3>
 __device__ __forceinline__ void mm_tile(const MmArgs &args, int tile, double2 *lds) {
     using Cfg = MmCfg;
     const int flags = args.flags;
@@ -170,7 +171,7 @@ __device__ __forceinline__ void mm_tile(const MmArgs &args, int tile, double2 *l
     t.sel = nullptr;
     t.qscale = nullptr;
     Acc<Cfg> acc;
-    ztile_direct<Cfg>(t, m0, i1, n0, j1, acc, lds);
+    ztile_direct<Cfg, NSEG, false, false, G3>(t, m0, i1, n0, j1, acc, lds);
 
     const bool lower = flags & (MM_LOWER | MM_MASK);
     const bool upper = flags & MM_UPPER;
@@ -205,11 +206,11 @@ __device__ __forceinline__ void mm_tile(const MmArgs &args, int tile, double2 *l
 
 // Blocks loop over the tiles (a launch may have fewer blocks than tiles when
 // it runs beside latency-critical work).
-template <int NSEG>
+template <int NSEG, bool G3>
 __global__ void __launch_bounds__(MmCfg::NT) k_gep_mm(const MmArgs args) {
     __shared__ double2 lds[MmCfg::LDS_ELEMS];
     for (int tile = blockIdx.x; tile < args.total; tile += gridDim.x) {
-        mm_tile<NSEG>(args, tile, lds);
+        mm_tile<NSEG, G3>(args, tile, lds);
         __syncthreads();   // LDS is reused by the next tile
     }
 }
@@ -539,6 +540,7 @@ struct Gep {
     int *info;
     hipStream_t st;
     int cap;   // most blocks per product launch (0: one per tile)
+    bool g3;   // products in the 3M form
 };
 
 #define GEP_TRY(x)                              \
@@ -589,10 +591,15 @@ hipError_t mm_batch(const Gep &g, const double2 *P, const double2 *Q, double2 *C
         if (a.njobs == 0) continue;
         a.total = (int)nblk;
         const long long grid = g.cap > 0 && nblk > g.cap ? g.cap : nblk;
-        if (P2)
-            hipLaunchKernelGGL(k_gep_mm<2>, dim3((unsigned)grid), dim3(Cfg::NT), 0, g.st, a);
+        const dim3 gd((unsigned)grid), bd(Cfg::NT);
+        if (P2 && g.g3)
+            hipLaunchKernelGGL((k_gep_mm<2, true>), gd, bd, 0, g.st, a);
+        else if (P2)
+            hipLaunchKernelGGL((k_gep_mm<2, false>), gd, bd, 0, g.st, a);
+        else if (g.g3)
+            hipLaunchKernelGGL((k_gep_mm<1, true>), gd, bd, 0, g.st, a);
         else
-            hipLaunchKernelGGL(k_gep_mm<1>, dim3((unsigned)grid), dim3(Cfg::NT), 0, g.st, a);
+            hipLaunchKernelGGL((k_gep_mm<1, false>), gd, bd, 0, g.st, a);
         GEP_TRY(hipGetLastError());
     }
     return hipSuccess;
@@ -829,7 +836,7 @@ size_t gep_workspace_bytes(int N) {
 }
 
 hipError_t launch_gep(const double2 *H, const double2 *S, int N, double2 *L, double2 *Ht,
-                      int *info, char *ws, hipStream_t st) {
+                      int *info, char *ws, hipStream_t st, bool g3) {
     const bool two = N >= GEP_HER2K_MIN_N;   // Ht from WH (two-term product), else from V
     const size_t m = padded(16 * (size_t)N * (size_t)N);
     Gep g;
@@ -842,6 +849,7 @@ hipError_t launch_gep(const double2 *H, const double2 *S, int N, double2 *L, dou
     g.N = N;
     g.info = info ? info : reinterpret_cast<int *>(ws + 5 * m);
     g.st = st;
+    g.g3 = g3;
     const long long nn = (long long)N * N;
     hipLaunchKernelGGL(k_gep_init, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, H, S, L,
                        g.M, g.MH, g.LH, two ? g.HL : nullptr, N);

@@ -31,7 +31,7 @@ def _declared():
 def test_header_declares_entry_points():
     names = _declared()
     for want in ("hs_build", "hs_build_ex", "hs_workspace_bytes", "hs_status_string",
-                 "hs_gep_reduce", "hs_gep_workspace_bytes"):
+                 "hs_gep_reduce", "hs_gep_reduce_ex", "hs_gep_workspace_bytes"):
         assert want in names
 
 
@@ -222,3 +222,6 @@ def test_gep_argument_checks():
         a = list(args)
         a[pos] = bad
         assert lib.hs_gep_reduce(*a) == -(pos + 1)
+        assert lib.hs_gep_reduce_ex(*a, P.HS_FP64_3M) == -(pos + 1)
+    for bad_mode in (P.HS_SPLIT_F16, P.HS_SPLIT_I8, 4, -1):
+        assert lib.hs_gep_reduce_ex(*args, bad_mode) == -10

@@ -42,11 +42,11 @@ def _random_pair(N, seed, shift=None):
     return H, S
 
 
-def _gep_gpu(H, S, stream=None, upper_garbage=False):
+def _gep_gpu(H, S, stream=None, upper_garbage=False, mode=0):
     from paper_1611_00606_amd import hs_gep_reduce
     torch = _torch()
     N = H.shape[0]
-    print(f"gep N={N}", flush=True)
+    print(f"gep N={N} mode={mode}", flush=True)
     dev = torch.device("cuda:0")
     Sd = S.copy()
     if upper_garbage:
@@ -56,7 +56,7 @@ def _gep_gpu(H, S, stream=None, upper_garbage=False):
     L = torch.full((N, N), 7 + 7j, dtype=torch.complex128, device=dev)
     Ht = torch.full((N, N), 7 + 7j, dtype=torch.complex128, device=dev)
     info = torch.full((1,), -5, dtype=torch.int32, device=dev)
-    hs_gep_reduce(Hg, Sg, L, Ht, info=info, stream=stream)
+    hs_gep_reduce(Hg, Sg, L, Ht, info=info, stream=stream, mode=mode)
     torch.cuda.synchronize()
     assert np.array_equal(Hg.cpu().numpy(), H, equal_nan=True), "H modified"
     assert np.array_equal(Sg.cpu().numpy(), Sd, equal_nan=True), "S modified"
@@ -133,7 +133,7 @@ def test_eigenvalues_match_generalized_problem():
     assert err <= TOL
 
 
-def _built(p, name):
+def _built(p, name, mode=0):
     from paper_1611_00606_amd import DeviceBuild, hs_gep_reduce
     torch = _torch()
     r = DeviceBuild.from_problem(p)
@@ -143,8 +143,8 @@ def _built(p, name):
     L = torch.empty_like(r.H)
     Ht = torch.empty_like(r.H)
     info = torch.zeros(1, dtype=torch.int32, device=r.H.device)
-    print(f"gep of built {name} N={p.N_G}", flush=True)
-    hs_gep_reduce(r.H, r.S, L, Ht, info=info)
+    print(f"gep of built {name} N={p.N_G} mode={mode}", flush=True)
+    hs_gep_reduce(r.H, r.S, L, Ht, info=info, mode=mode)
     torch.cuda.synchronize()
     return H, S, L.cpu().numpy(), Ht.cpu().numpy(), int(info.item())
 
@@ -331,3 +331,65 @@ def test_largest_size_residuals():
         err = np.linalg.norm(Ht[:, j].cpu().numpy() - col) / np.linalg.norm(col)
         print(f"  column {j} rel err {err:.2e}", flush=True)
         assert err <= TOL
+
+
+# ---------------------------------------------------------------------------
+# The products in the 3M form (hs_gep_reduce_ex with HS_FP64_3M). The 128x128
+# diagonal blocks are still factored and inverted in the 4-product form; the
+# 3M products change only the rounding (the imaginary parts' bound grows by a
+# small constant factor), so the same bars hold.
+
+@pytest.mark.parametrize("N", [65, 300, 1100, 4200])
+def test_3m_random_pairs(N):
+    from paper_1611_00606_amd import HS_FP64_3M
+    H, S = _random_pair(N, seed=700 + N)
+    _check(H, S, *_gep_gpu(H, S, mode=HS_FP64_3M))
+
+
+def test_3m_built_overlap_and_hamiltonian():
+    from paper_1611_00606_amd import HS_FP64_3M
+    _check(*_built(BUILT["plain_gpu"](), "plain_gpu", mode=HS_FP64_3M))
+
+
+def test_3m_differs_from_fp64_by_rounding_and_is_deterministic():
+    from paper_1611_00606_amd import HS_FP64, HS_FP64_3M
+    H, S = _random_pair(1100, seed=71)
+    L4, Ht4, i4 = _gep_gpu(H, S, mode=HS_FP64)
+    L3, Ht3, i3 = _gep_gpu(H, S, mode=HS_FP64_3M)
+    L3b, Ht3b, _ = _gep_gpu(H, S, mode=HS_FP64_3M)
+    assert i4 == i3 == 0
+    assert np.array_equal(L3, L3b) and np.array_equal(Ht3, Ht3b)
+    assert not np.array_equal(Ht3, Ht4)   # the mode reached other kernels
+    assert _rel(L3, L4) <= TOL and _rel(Ht3, Ht4) <= TOL
+
+
+def test_3m_failing_pivot_index():
+    from paper_1611_00606_amd import HS_FP64_3M
+    H, S = _random_pair(300, seed=72)
+    S[200, 200] = -1.0   # leading minor 201 not positive definite
+    _, _, info = _gep_gpu(H, S, mode=HS_FP64_3M)
+    assert info == O.gep_reduce(H, S)[2]
+
+
+def test_3m_full_size_residuals():
+    """N = 8000 in the 3M form: S = L L^H and H = L Ht L^H to the same
+    backward-error bars as the 4-product form."""
+    from paper_1611_00606_amd import DeviceBuild, HS_FP64_3M, hs_gep_reduce
+    torch = _torch()
+    p = make_config("precision", seed=0)
+    r = DeviceBuild.from_problem(p)
+    r.run()
+    torch.cuda.synchronize()
+    L = torch.empty_like(r.H)
+    Ht = torch.empty_like(r.H)
+    info = torch.zeros(1, dtype=torch.int32, device=r.H.device)
+    print(f"gep 3M of built precision N={p.N_G}", flush=True)
+    hs_gep_reduce(r.H, r.S, L, Ht, info=info, mode=HS_FP64_3M)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    r1 = torch.linalg.matrix_norm(L @ L.conj().T - r.S) / torch.linalg.matrix_norm(r.S)
+    r2 = torch.linalg.matrix_norm(L @ Ht @ L.conj().T - r.H) / torch.linalg.matrix_norm(r.H)
+    print(f"  residual S {r1.item():.2e} H {r2.item():.2e}", flush=True)
+    assert r1.item() <= 1e-13 and r2.item() <= 1e-12
+    assert torch.equal(Ht, Ht.conj().T)
+    assert torch.count_nonzero(torch.triu(L, 1)).item() == 0
