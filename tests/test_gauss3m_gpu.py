@@ -9,7 +9,8 @@ balanced term, so the relative Frobenius error of H and S stays far inside the
 about 1e-14 at K = 8100). The tests check that bar against the oracle, that
 the mode really takes another kernel (results differ from HS_FP64 in the
 last bits), exact Hermitian symmetry and the branch flags, and that the
-serving context computes the same bits as the one-shot build.
+serving context and the batched per-atom stage lead to the same bits as the
+one-shot build with separate per-atom launches.
 """
 
 import numpy as np
@@ -79,6 +80,26 @@ def test_full_parity(name):
     assert np.array_equal(H, H.conj().T) and np.array_equal(S, S.conj().T)
     assert np.all(H.diagonal().imag == 0) and np.all(S.diagonal().imag == 0)
     assert np.array_equal(info, _expected_info(p))
+
+
+def test_batched_per_atom_stage():
+    """The batched per-atom stage (one persistent launch, a tile shape per
+    N_L) feeding the 3M reductions: against the oracle, and bitwise equal to
+    the separate launches feeding the same reductions."""
+    from paper_1611_00606_amd import DeviceBuild, HS_FP64_3M
+    torch = _torch()
+    p = make_problem(6, [16, 49, 81, 121, 1, 128], 700, seed=8, fail_atoms=[2], planted={3: 50})
+    print(f"case mixed_nl batched mode={HS_FP64_3M}", flush=True)
+    r = DeviceBuild.from_problem(p, mode=HS_FP64_3M, batch=1)
+    r.run()
+    torch.cuda.synchronize()
+    H, S, info = r.results()
+    Hr = O.hamiltonian(p.A, p.B, p.T_AA, p.T_AB, p.T_BB, p.nl)
+    Sr = O.overlap(p.A, p.B, p.U, p.nl)
+    assert _rel(H, Hr) <= TOL and _rel(S, Sr) <= TOL
+    assert np.array_equal(info, _expected_info(p))
+    H1, S1, _ = _build(p, HS_FP64_3M).results()
+    assert np.array_equal(H, H1) and np.array_equal(S, S1)
 
 
 def test_differs_from_four_product_form_in_the_last_bits():
