@@ -292,6 +292,26 @@ int hs_gep_reduce_ex(const hs_complex *H, const hs_complex *S, int N,
                      hs_complex *L, hs_complex *Ht, int32_t *info,
                      void *workspace, size_t workspace_bytes, void *stream, int mode);
 
+/*
+ * hs_gep_check_schedule - race check of the reduction's stream schedule,
+ * host only (no device, no HIP call, nothing allocated on a device). Runs
+ * the orchestration of hs_gep_reduce_ex for 1 N and 2 mode (HS_FP64 or
+ * HS_FP64_3M) without issuing anything, recording every launch with its
+ * stream and the rectangles of each matrix it reads and writes, and every
+ * event record and stream wait; then checks with vector clocks that every
+ * two launches on different streams that touch a common 128 x 128 cell of a
+ * matrix, one of them writing, are ordered by stream order and event waits.
+ *   3 drop_wait  0, or a wait site (1..10, in the order the library's
+ *         schedule defines them) whose waits are left out: a test hook that
+ *         shows the check finds the race a missing wait opens
+ *   4 report, 5 report_len  host buffer (or NULL) for a NUL-terminated
+ *         description of the first few unordered pairs
+ * Returns the number of unordered pairs (0: every conflict is ordered), -1
+ * for N < 1, -2 for another mode, -6 if the orchestration reported an
+ * error.
+ */
+int hs_gep_check_schedule(int N, int mode, int drop_wait, char *report, size_t report_len);
+
 /* ------------------------------------------------------------------------
  * Resident context: one atom set, many k-points.
  *

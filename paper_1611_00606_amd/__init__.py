@@ -49,5 +49,6 @@ from ._binding import (  # noqa: F401,E402
     hs_autotune_atoms,
     hs_gep_workspace_bytes,
     hs_gep_reduce,
+    hs_gep_check_schedule,
 )
 from .runner import DeviceBuild  # noqa: F401,E402

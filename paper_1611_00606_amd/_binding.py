@@ -151,6 +151,8 @@ def load_library() -> ctypes.CDLL:
     lib.hs_gep_reduce.restype = i32
     lib.hs_gep_reduce_ex.argtypes = [vp, vp, i32, vp, vp, vp, vp, sz, vp, i32]
     lib.hs_gep_reduce_ex.restype = i32
+    lib.hs_gep_check_schedule.argtypes = [i32, i32, i32, ctypes.c_char_p, sz]
+    lib.hs_gep_check_schedule.restype = i32
     _lib = lib
     return lib
 
@@ -407,6 +409,17 @@ def hs_autotune_atoms(nl_values, N_G, reps=3, stream=None):
 
 def hs_gep_workspace_bytes(N) -> int:
     return int(load_library().hs_gep_workspace_bytes(int(N)))
+
+
+def hs_gep_check_schedule(N: int, mode: int = HS_FP64, drop_wait: int = 0):
+    """(count, report): race check of the reduction's stream schedule for N
+    (host only, nothing is launched). count is the number of pairs of
+    launches on different streams that touch a common 128 x 128 cell, one
+    writing, with no ordering between them; negative for invalid arguments.
+    drop_wait leaves out one wait site (a test hook)."""
+    buf = ctypes.create_string_buffer(4096)
+    n = load_library().hs_gep_check_schedule(int(N), int(mode), int(drop_wait), buf, len(buf))
+    return int(n), buf.value.decode()
 
 
 def hs_gep_reduce(H, S, L, Ht, *, info=None, workspace=None, stream=None, check=True,

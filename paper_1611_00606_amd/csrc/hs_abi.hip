@@ -409,6 +409,19 @@ int hs_gep_reduce_ex(const hs_complex *H, const hs_complex *S, int N, hs_complex
     return e == hipSuccess ? HS_OK : hs::hip_fail(e, "hs_gep_reduce launch");
 }
 
+int hs_gep_check_schedule(int N, int mode, int drop_wait, char *report, size_t report_len) {
+    if (N < 1) return -1;
+    if (mode != HS_FP64 && mode != HS_FP64_3M) return -2;
+    std::string rep;
+    const int n = hs::gep_check_schedule(N, mode == HS_FP64_3M, drop_wait, rep);
+    if (report && report_len) {
+        const size_t k = std::min(rep.size(), report_len - 1);
+        std::memcpy(report, rep.data(), k);
+        report[k] = '\0';
+    }
+    return n < 0 ? -6 : n;
+}
+
 const char *hs_status_string(int status) {
     const std::string &m = hs::last_error();
     switch (status) {

@@ -104,6 +104,11 @@ hipError_t launch_mirror1(double2 *M, int n, hipStream_t st);
 size_t gep_workspace_bytes(int N);
 hipError_t launch_gep(const double2 *H, const double2 *S, int N, double2 *L, double2 *Ht,
                       int *info, char *ws, hipStream_t st, bool g3);
+// Runs launch_gep's orchestration without issuing anything and checks that
+// every pair of launches on different streams that touch a common 128 x 128
+// cell of a matrix (one writing) is ordered; returns the number of pairs
+// that are not (-1 if the orchestration failed), describing a few in report.
+int gep_check_schedule(int N, bool g3, int drop_tag, std::string &report);
 
 // ---------------------------------------------------------------------------
 // Host-side plan of one atom set and the enqueue steps shared by the one-shot

@@ -33,7 +33,10 @@
 // M = L^{-1} and MH = L^{-H} (zero outside their triangles), W (S21^H,
 // L21 M11), Ht (output).
 #include <algorithm>
+#include <cstdint>
 #include <mutex>
+#include <set>
+#include <string>
 #include <vector>
 
 #include "hs_internal.h"
@@ -553,6 +556,214 @@ struct Rect {
     int i0, i1, j0, j1, k0, k1;
 };
 
+// ---------------------------------------------------------------------------
+// Schedule check (host only). With a recorder installed the orchestration
+// below runs unchanged but issues nothing: every launch is logged with its
+// stream and the rectangles of each matrix it reads and writes (per output
+// tile, with the tile's trimmed contraction range), every event record and
+// stream wait with its stream and event. sched_check then runs a
+// vector-clock pass over the log: two launches on different streams that
+// touch a common 128 x 128 cell of a matrix, one of them writing, must be
+// ordered by a chain of stream order and event waits.
+enum SchedBuf { SB_H, SB_S, SB_L, SB_HT, SB_LH, SB_M, SB_MH, SB_W, SB_HL, SB_INFO, SB_COUNT };
+const char *const kSchedBufName[SB_COUNT] = {"H", "S", "L", "Ht", "LH", "M", "MH", "W", "HL", "info"};
+
+struct SchedAcc {
+    int buf, r0, r1, c0, c1;   // element rectangle [r0, r1) x [c0, c1)
+    bool write;
+};
+struct SchedOp {
+    int kind;          // 0 launch, 1 event record, 2 stream wait
+    hipStream_t st;
+    hipEvent_t ev;
+    const char *name;
+    std::vector<SchedAcc> acc;
+};
+struct Sched {
+    std::vector<SchedOp> ops;
+    const void *base[SB_COUNT] = {};
+    int drop_tag = 0;            // waits with this tag are left out (a test hook)
+    uintptr_t next_event = 1;
+    int buf(const void *p) const {
+        for (int i = 0; i < SB_COUNT; ++i)
+            if (base[i] == p) return i;
+        return -1;
+    }
+    SchedOp &launch(hipStream_t st, const char *name) {
+        ops.push_back(SchedOp{0, st, nullptr, name, {}});
+        return ops.back();
+    }
+    void add(SchedOp &op, const void *p, int r0, int r1, int c0, int c1, bool write) {
+        const int b = buf(p);
+        if (b >= 0 && r1 > r0 && c1 > c0) op.acc.push_back(SchedAcc{b, r0, r1, c0, c1, write});
+    }
+};
+thread_local Sched *g_sched = nullptr;
+
+hipError_t ev_create(hipEvent_t *e) {
+    if (g_sched) {
+        *e = reinterpret_cast<hipEvent_t>(g_sched->next_event++);
+        return hipSuccess;
+    }
+    return hipEventCreateWithFlags(e, hipEventDisableTiming);
+}
+void ev_destroy(hipEvent_t e) {
+    if (!g_sched && e) (void)hipEventDestroy(e);
+}
+hipError_t ev_record(hipEvent_t e, hipStream_t st) {
+    if (g_sched) {
+        g_sched->ops.push_back(SchedOp{1, st, e, "record", {}});
+        return hipSuccess;
+    }
+    return hipEventRecord(e, st);
+}
+// Wait sites, by tag (hs_gep_check_schedule's drop argument).
+enum WaitTag {
+    WT_TRANSPOSE_AFTER_BLOCK = 1,   // next S21^H after the next column block's update
+    WT_PANEL_AFTER_TRANSPOSE,       // panel product after S21^H
+    WT_BLOCK_AFTER_BULK,            // next column block after the previous bulk update
+    WT_AHEAD_AFTER_PANEL,           // L21 and bulk update after the panel product
+    WT_JOIN_AHEAD,                  // end of the factorization: lookahead stream
+    WT_JOIN_TRANSPOSE,              // end of the factorization: transposes stream
+    WT_FORK,                        // background stream after the top split's panel
+    WT_FORK_AHEAD,                  // background stream after the pending lookahead work
+    WT_END_AFTER_INVERSE,           // top split's M21 after the leading block's inverse
+    WT_END_AFTER_BACKGROUND         // Ht's last rows after the background's products
+};
+hipError_t ev_wait(hipStream_t st, hipEvent_t e, int tag) {
+    if (g_sched) {
+        if (tag != g_sched->drop_tag) g_sched->ops.push_back(SchedOp{2, st, e, "wait", {}});
+        return hipSuccess;
+    }
+    return hipStreamWaitEvent(st, e, 0);
+}
+
+// The vector-clock pass. Returns the number of unordered conflicting pairs
+// of launches and describes the first few in `report`.
+int sched_check(const Sched &sc, int N, std::string &report) {
+    constexpr int CB = 128;
+    const int nc = (N + CB - 1) / CB;
+    std::vector<hipStream_t> streams;
+    auto sid = [&](hipStream_t st) {
+        for (size_t i = 0; i < streams.size(); ++i)
+            if (streams[i] == st) return (int)i;
+        streams.push_back(st);
+        return (int)streams.size() - 1;
+    };
+    for (const SchedOp &op : sc.ops) sid(op.st);
+    const int ns = (int)streams.size();
+    std::vector<std::vector<int>> vc(ns, std::vector<int>(ns, 0));
+    std::vector<std::pair<hipEvent_t, std::vector<int>>> evc;
+    struct Last {
+        int op = -1, st = 0, clk = 0;
+    };
+    struct CellState {
+        Last w;
+        std::vector<Last> r;   // latest read per stream since the last write
+    };
+    const size_t ncell = (size_t)SB_COUNT * nc * nc;
+    std::vector<CellState> cells(ncell);
+    std::vector<signed char> mark(ncell, -1);   // per launch: 0 read, 1 write
+    std::vector<size_t> touched;
+    std::set<std::pair<int, int>> races;
+    for (int i = 0; i < (int)sc.ops.size(); ++i) {
+        const SchedOp &op = sc.ops[i];
+        const int s = sid(op.st);
+        if (op.kind == 1) {
+            bool found = false;
+            for (auto &e : evc)
+                if (e.first == op.ev) {
+                    e.second = vc[s];
+                    found = true;
+                }
+            if (!found) evc.push_back({op.ev, vc[s]});
+            continue;
+        }
+        if (op.kind == 2) {
+            for (auto &e : evc)
+                if (e.first == op.ev)
+                    for (int k = 0; k < ns; ++k) vc[s][k] = std::max(vc[s][k], e.second[k]);
+            continue;
+        }
+        ++vc[s][s];
+        const std::vector<int> &me = vc[s];
+        touched.clear();
+        for (const SchedAcc &a : op.acc) {
+            const int cr0 = a.buf == SB_INFO ? 0 : a.r0 / CB, cr1 = a.buf == SB_INFO ? 0 : (a.r1 - 1) / CB;
+            const int cc0 = a.buf == SB_INFO ? 0 : a.c0 / CB, cc1 = a.buf == SB_INFO ? 0 : (a.c1 - 1) / CB;
+            for (int r = cr0; r <= cr1; ++r)
+                for (int c = cc0; c <= cc1; ++c) {
+                    const size_t id = ((size_t)a.buf * nc + r) * nc + c;
+                    if (mark[id] < 0) touched.push_back(id);
+                    mark[id] = std::max<signed char>(mark[id], a.write ? 1 : 0);
+                }
+        }
+        auto ordered = [&](const Last &l) { return l.st == s || me[l.st] >= l.clk; };
+        auto race = [&](int other, size_t id) {
+            if (races.count({other, i})) return;
+            if (races.size() < 5) {
+                const int b = (int)(id / ((size_t)nc * nc));
+                const int r = (int)(id / nc % nc), c = (int)(id % nc);
+                report += std::string(sc.ops[other].name) + " and " + op.name + " on " +
+                          kSchedBufName[b] + " cell (" + std::to_string(r) + ", " +
+                          std::to_string(c) + "); ";
+            }
+            races.insert({other, i});
+        };
+        for (size_t id : touched) {
+            CellState &cs = cells[id];
+            const bool w = mark[id] == 1;
+            mark[id] = -1;
+            if (cs.w.op >= 0 && !ordered(cs.w)) race(cs.w.op, id);
+            if (w) {
+                for (const Last &l : cs.r)
+                    if (!ordered(l)) race(l.op, id);
+                cs.r.clear();
+                cs.w = Last{i, s, me[s]};
+            } else {
+                bool had = false;
+                for (Last &l : cs.r)
+                    if (l.st == s) {
+                        l = Last{i, s, me[s]};
+                        had = true;
+                    }
+                if (!had) cs.r.push_back(Last{i, s, me[s]});
+            }
+        }
+    }
+    return (int)races.size();
+}
+
+// The footprint of one product launch, tile by tile as mm_tile trims it.
+void sched_mm(const Gep &g, const MmArgs &a) {
+    using Cfg = MmCfg;
+    SchedOp &op = g_sched->launch(g.st, a.P2 ? "k_gep_mm<2>" : "k_gep_mm<1>");
+    const int flags = a.flags;
+    for (int jb = 0; jb < a.njobs; ++jb) {
+        const MmJob &j = a.job[jb];
+        for (int ti = 0; ti < j.ntr; ++ti)
+            for (int tj = 0; tj < j.ntc; ++tj) {
+                if ((flags & MM_UPPER) && tj < ti) continue;
+                if ((flags & MM_LOWER) && tj > ti) continue;
+                const int m0 = j.i0 + ti * Cfg::BM, n0 = j.j0 + tj * Cfg::BN;
+                if (m0 >= j.i1 || n0 >= j.j1) continue;
+                const int m1 = std::min(m0 + Cfg::BM, j.i1), n1 = std::min(n0 + Cfg::BN, j.j1);
+                int klo = j.k0, khi = j.k1;
+                if (flags & MM_PU) khi = std::min(khi, m0 + Cfg::BM);
+                if (flags & MM_QU) khi = std::min(khi, n0 + Cfg::BN);
+                if (flags & MM_QL) klo = std::max(klo, n0);
+                if (flags & MM_PL) klo = std::max(klo, m0);
+                g_sched->add(op, a.P, klo, khi, m0, m1, false);
+                g_sched->add(op, a.Q, klo, khi, n0, n1, false);
+                if (a.P2) {
+                    g_sched->add(op, a.P2, klo, khi, m0, m1, false);
+                    g_sched->add(op, a.Q2, klo, khi, n0, n1, false);
+                }
+                g_sched->add(op, a.C, m0, m1, n0, n1, true);
+            }
+    }
+}
+
 // Products over the rectangles r[0 .. n), up to MM_JOBS per launch.
 hipError_t mm_batch(const Gep &g, const double2 *P, const double2 *Q, double2 *C, const Rect *r,
                     int n, int flags, int op, const double2 *P2 = nullptr,
@@ -590,6 +801,10 @@ hipError_t mm_batch(const Gep &g, const double2 *P, const double2 *Q, double2 *C
         }
         if (a.njobs == 0) continue;
         a.total = (int)nblk;
+        if (g_sched) {
+            sched_mm(g, a);
+            continue;
+        }
         const long long grid = g.cap > 0 && nblk > g.cap ? g.cap : nblk;
         const dim3 gd((unsigned)grid), bd(Cfg::NT);
         if (P2 && g.g3)
@@ -627,6 +842,14 @@ hipError_t conj_t_batch(const Gep &g, const double2 *X, double2 *D, const Rect *
             ++nj;
         }
         if (nj == 0) continue;
+        if (g_sched) {
+            SchedOp &op = g_sched->launch(g.st, "k_gep_conj_t");
+            for (int t = 0; t < nj; ++t) {
+                g_sched->add(op, X, j.r[t][0], j.r[t][1], j.r[t][2], j.r[t][3], false);
+                g_sched->add(op, D, j.r[t][2], j.r[t][3], j.r[t][0], j.r[t][1], true);
+            }
+            continue;
+        }
         hipLaunchKernelGGL(k_gep_conj_t, dim3(gx, gy, nj), dim3(256), 0, g.st, X, D, g.N, j);
         GEP_TRY(hipGetLastError());
     }
@@ -644,6 +867,7 @@ hipError_t conj_t(const Gep &g, const double2 *X, double2 *D, int i0, int i1, in
 // process); default priority,
 // created once and kept for the life of the process.
 hipStream_t aux_stream(int which) {
+    if (g_sched) return reinterpret_cast<hipStream_t>((uintptr_t)(0x100 + which));
     static std::mutex mu;
     static hipStream_t cached[64][3] = {};
     int dev = 0;
@@ -678,21 +902,19 @@ hipError_t factor(const Gep &g, Hook after_panel) {
     if (ahead) {
         ga.st = aux_stream(0);
         gc.st = aux_stream(2);
-        ahead = ga.st != nullptr && gc.st != nullptr &&
-                hipEventCreateWithFlags(&e_panel, hipEventDisableTiming) == hipSuccess &&
-                hipEventCreateWithFlags(&e_bulk, hipEventDisableTiming) == hipSuccess &&
-                hipEventCreateWithFlags(&e_next, hipEventDisableTiming) == hipSuccess &&
-                hipEventCreateWithFlags(&e_w, hipEventDisableTiming) == hipSuccess;
+        ahead = ga.st != nullptr && gc.st != nullptr && ev_create(&e_panel) == hipSuccess &&
+                ev_create(&e_bulk) == hipSuccess && ev_create(&e_next) == hipSuccess &&
+                ev_create(&e_w) == hipSuccess;
     }
     // recorded events still to be waited for (no wait on an unrecorded event)
     bool bulk_pending = false, w_pending = false;
     hipError_t err = hipSuccess;
     // S21^H of the first panel, beside the first leaf
     const auto next_s21h = [&](int c0, int c1) -> hipError_t {   // columns [c0, c1)
-        GEP_TRY(hipEventRecord(e_next, g.st));
-        GEP_TRY(hipStreamWaitEvent(gc.st, e_next, 0));
+        GEP_TRY(ev_record(e_next, g.st));
+        GEP_TRY(ev_wait(gc.st, e_next, WT_TRANSPOSE_AFTER_BLOCK));
         GEP_TRY(conj_t(gc, g.L, g.W, c1, N, c0, c1));
-        GEP_TRY(hipEventRecord(e_w, gc.st));
+        GEP_TRY(ev_record(e_w, gc.st));
         w_pending = true;
         return hipSuccess;
     };
@@ -700,9 +922,18 @@ hipError_t factor(const Gep &g, Hook after_panel) {
     for (int kb = 0; kb < N && err == hipSuccess; kb += LB) {
         const int nb = N - kb < LB ? N - kb : LB;
         const int t0 = kb + nb;
-        hipLaunchKernelGGL(k_gep_leaf, dim3(1), dim3(512), 0, g.st, g.L, g.M, g.MH, N, kb, nb,
-                           g.info);
-        if ((err = hipGetLastError()) != hipSuccess || t0 >= N) break;
+        if (g_sched) {
+            SchedOp &op = g_sched->launch(g.st, "k_gep_leaf");
+            for (const double2 *X : {(const double2 *)g.L, (const double2 *)g.M,
+                                     (const double2 *)g.MH})
+                g_sched->add(op, X, kb, kb + nb, kb, kb + nb, true);
+            g_sched->add(op, g.info, 0, 1, 0, 1, true);
+        } else {
+            hipLaunchKernelGGL(k_gep_leaf, dim3(1), dim3(512), 0, g.st, g.L, g.M, g.MH, N, kb, nb,
+                               g.info);
+            err = hipGetLastError();
+        }
+        if (err != hipSuccess || t0 >= N) break;
         if (!ahead) {
             if ((err = conj_t(g, g.L, g.W, t0, N, kb, t0)) != hipSuccess) break;  // W = S21^H
             if ((err = mm(g, g.MH, g.W, g.LH, kb, t0, t0, N, kb, t0, MM_PU, OP_STORE)) !=
@@ -713,7 +944,7 @@ hipError_t factor(const Gep &g, Hook after_panel) {
             err = mm(g, g.LH, g.LH, g.L, t0, N, t0, N, kb, t0, MM_LOWER, OP_SUB);  // S22 -= L21 L21^H
             continue;
         }
-        if ((err = hipStreamWaitEvent(g.st, e_w, 0)) != hipSuccess) break;        // W = S21^H
+        if ((err = ev_wait(g.st, e_w, WT_PANEL_AFTER_TRANSPOSE)) != hipSuccess) break;   // W = S21^H
         w_pending = false;
         if ((err = mm(g, g.MH, g.W, g.LH, kb, t0, t0, N, kb, t0, MM_PU, OP_STORE)) != hipSuccess)
             break;                                                                 // LH21 = M11 S21^H
@@ -721,14 +952,14 @@ hipError_t factor(const Gep &g, Hook after_panel) {
         // which orders that stream's pending work before anything it forks
         if ((err = after_panel(t0, bulk_pending ? e_bulk : nullptr)) != hipSuccess) break;
         const int t1 = N - t0 < LB ? N : t0 + LB;
-        if ((err = hipEventRecord(e_panel, g.st)) != hipSuccess) break;
-        if (bulk_pending && (err = hipStreamWaitEvent(g.st, e_bulk, 0)) != hipSuccess) break;
-        if ((err = hipStreamWaitEvent(ga.st, e_panel, 0)) != hipSuccess) break;
+        if ((err = ev_record(e_panel, g.st)) != hipSuccess) break;
+        if (bulk_pending && (err = ev_wait(g.st, e_bulk, WT_BLOCK_AFTER_BULK)) != hipSuccess) break;
+        if ((err = ev_wait(ga.st, e_panel, WT_AHEAD_AFTER_PANEL)) != hipSuccess) break;
         if ((err = conj_t(ga, g.LH, g.L, kb, t0, t0, N)) != hipSuccess) break;    // L21
         if (t1 < N && (err = mm(ga, g.LH, g.LH, g.L, t1, N, t1, N, kb, t0, MM_LOWER, OP_SUB)) !=
                           hipSuccess)
             break;                                                                 // the rest
-        if ((err = hipEventRecord(e_bulk, ga.st)) != hipSuccess) break;
+        if ((err = ev_record(e_bulk, ga.st)) != hipSuccess) break;
         bulk_pending = true;
         if ((err = mm(g, g.LH, g.LH, g.L, t0, N, t0, t1, kb, t0, MM_MASK, OP_SUB)) != hipSuccess)
             break;                                                                 // next column block
@@ -736,15 +967,14 @@ hipError_t factor(const Gep &g, Hook after_panel) {
     }
     // join the other streams, also after an error
     if (bulk_pending) {
-        const hipError_t e = hipStreamWaitEvent(g.st, e_bulk, 0);
+        const hipError_t e = ev_wait(g.st, e_bulk, WT_JOIN_AHEAD);
         if (err == hipSuccess) err = e;
     }
     if (w_pending) {
-        const hipError_t e = hipStreamWaitEvent(g.st, e_w, 0);
+        const hipError_t e = ev_wait(g.st, e_w, WT_JOIN_TRANSPOSE);
         if (err == hipSuccess) err = e;
     }
-    for (hipEvent_t e : {e_panel, e_bulk, e_next, e_w})
-        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : {e_panel, e_bulk, e_next, e_w}) ev_destroy(e);
     return err;
 }
 
@@ -851,11 +1081,34 @@ hipError_t launch_gep(const double2 *H, const double2 *S, int N, double2 *L, dou
     g.st = st;
     g.g3 = g3;
     const long long nn = (long long)N * N;
-    hipLaunchKernelGGL(k_gep_init, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, H, S, L,
-                       g.M, g.MH, g.LH, two ? g.HL : nullptr, N);
-    GEP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_gep_info_clear, dim3(1), dim3(1), 0, st, g.info);
-    GEP_TRY(hipGetLastError());
+    // Ht's upper triangle by conjugation, Im(diag) = 0
+    const auto mirror = [&]() -> hipError_t {
+        if (g_sched) {
+            g_sched->add(g_sched->launch(st, "k_mirror"), Ht, 0, N, 0, N, true);
+            return hipSuccess;
+        }
+        return launch_mirror1(Ht, N, st);
+    };
+    if (g_sched) {
+        const void *b[SB_COUNT] = {H, S, L, Ht, g.LH, g.M, g.MH, g.W, g.HL, g.info};
+        std::copy(b, b + SB_COUNT, g_sched->base);
+        SchedOp &op = g_sched->launch(st, "k_gep_init");
+        g_sched->add(op, S, 0, N, 0, N, false);
+        for (const void *X : {(const void *)L, (const void *)g.M, (const void *)g.MH,
+                              (const void *)g.LH})
+            g_sched->add(op, X, 0, N, 0, N, true);
+        if (two) {
+            g_sched->add(op, H, 0, N, 0, N, false);
+            g_sched->add(op, g.HL, 0, N, 0, N, true);
+        }
+        g_sched->add(op, g.info, 0, 1, 0, 1, true);
+    } else {
+        hipLaunchKernelGGL(k_gep_init, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, H, S,
+                           L, g.M, g.MH, g.LH, two ? g.HL : nullptr, N);
+        GEP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_gep_info_clear, dim3(1), dim3(1), 0, st, g.info);
+        GEP_TRY(hipGetLastError());
+    }
     g.cap = 0;
     std::vector<std::vector<Node>> lv;
     tree(0, N, 0, lv);
@@ -872,7 +1125,7 @@ hipError_t launch_gep(const double2 *H, const double2 *S, int N, double2 *L, dou
             GEP_TRY(v_cols(g, H, 0, N));
             GEP_TRY(mm(g, g.LH, g.MH, Ht, 0, N, 0, N, 0, N, MM_QU | MM_LOWER, OP_STORE));  // V^H MH
         }
-        return launch_mirror1(Ht, N, st);
+        return mirror();
     }
     // Once the factorization has passed the top split m (the leaf and the
     // panel product LH21 of the panel ending at m are enqueued), the inverse of the
@@ -884,49 +1137,66 @@ hipError_t launch_gep(const double2 *H, const double2 *S, int N, double2 *L, dou
     const int mt = top.m;
     Gep gb = g;
     gb.st = sb;
-    gb.cap = num_cus() * HS_GEP_BG_QUARTERS / 4;
+    gb.cap = (g_sched ? 256 : num_cus()) * HS_GEP_BG_QUARTERS / 4;
     hipEvent_t e_split = nullptr, e_inv = nullptr, e_v = nullptr;
-    hipError_t err = hipEventCreateWithFlags(&e_split, hipEventDisableTiming);
-    if (err == hipSuccess) err = hipEventCreateWithFlags(&e_inv, hipEventDisableTiming);
-    if (err == hipSuccess) err = hipEventCreateWithFlags(&e_v, hipEventDisableTiming);
+    hipError_t err = ev_create(&e_split);
+    if (err == hipSuccess) err = ev_create(&e_inv);
+    if (err == hipSuccess) err = ev_create(&e_v);
     bool forked = false;
     const auto left = [mt](const Node &n) { return n.b <= mt; };
     if (err == hipSuccess)
         err = factor(g, [&](int t0, hipEvent_t e_ahead) -> hipError_t {
             if (t0 != mt) return hipSuccess;
-            GEP_TRY(hipEventRecord(e_split, st));
-            GEP_TRY(hipStreamWaitEvent(sb, e_split, 0));
+            GEP_TRY(ev_record(e_split, st));
+            GEP_TRY(ev_wait(sb, e_split, WT_FORK));
             // the previous panel's L21 = LH21^H may still read LH columns
             // >= m - LB on the lookahead stream; V (or WH) overwrites LH's
             // columns < m below
-            if (e_ahead) GEP_TRY(hipStreamWaitEvent(sb, e_ahead, 0));
+            if (e_ahead) GEP_TRY(ev_wait(sb, e_ahead, WT_FORK_AHEAD));
             forked = true;
             GEP_TRY(invert(gb, lv, left));
             GEP_TRY(node_w21(gb, {top}));   // L21 and M11 of the top split are final too
-            GEP_TRY(hipEventRecord(e_inv, sb));
+            GEP_TRY(ev_record(e_inv, sb));
             if (two) {
                 GEP_TRY(wh_cols(gb, 0, mt));
                 GEP_TRY(her2k_rows(gb, Ht, 0, mt));
             } else {
                 GEP_TRY(v_cols(gb, H, 0, mt));
             }
-            return hipEventRecord(e_v, sb);
+            return ev_record(e_v, sb);
         });
     if (err == hipSuccess) err = invert(g, lv, [mt](const Node &n) { return n.a >= mt; });
-    if (err == hipSuccess && forked) err = hipStreamWaitEvent(st, e_inv, 0);
+    if (err == hipSuccess && forked) err = ev_wait(st, e_inv, WT_END_AFTER_INVERSE);
     if (err == hipSuccess) err = node_m21(g, {top});
     if (err == hipSuccess) err = two ? wh_cols(g, mt, N) : v_cols(g, H, mt, N);
     if (forked) {   // join the second stream even after an error
-        const hipError_t e = hipStreamWaitEvent(st, e_v, 0);
+        const hipError_t e = ev_wait(st, e_v, WT_END_AFTER_BACKGROUND);
         if (err == hipSuccess) err = e;
     }
     if (err == hipSuccess)
         err = two ? her2k_rows(g, Ht, mt, N)
                   : mm(g, g.LH, g.MH, Ht, 0, N, 0, N, 0, N, MM_QU | MM_LOWER, OP_STORE);
-    for (hipEvent_t e : {e_split, e_inv, e_v})
-        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : {e_split, e_inv, e_v}) ev_destroy(e);
     GEP_TRY(err);
-    return launch_mirror1(Ht, N, st);
+    return mirror();
+}
+
+int gep_check_schedule(int N, bool g3, int drop_tag, std::string &report) {
+    Sched sc;
+    sc.drop_tag = drop_tag;
+    // distinct stand-in addresses; nothing is dereferenced or launched
+    auto fake = [](uintptr_t a) { return reinterpret_cast<double2 *>(a); };
+    char *ws = reinterpret_cast<char *>((uintptr_t)1 << 44);
+    g_sched = &sc;
+    const hipError_t e = launch_gep(fake((uintptr_t)1 << 40), fake((uintptr_t)2 << 40), N,
+                                    fake((uintptr_t)3 << 40), fake((uintptr_t)4 << 40), nullptr, ws,
+                                    reinterpret_cast<hipStream_t>((uintptr_t)0x10), g3);
+    g_sched = nullptr;
+    if (e != hipSuccess) {
+        report = "orchestration returned an error";
+        return -1;
+    }
+    return sched_check(sc, N, report);
 }
 
 }  // namespace hs

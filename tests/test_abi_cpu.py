@@ -31,7 +31,8 @@ def _declared():
 def test_header_declares_entry_points():
     names = _declared()
     for want in ("hs_build", "hs_build_ex", "hs_workspace_bytes", "hs_status_string",
-                 "hs_gep_reduce", "hs_gep_reduce_ex", "hs_gep_workspace_bytes"):
+                 "hs_gep_reduce", "hs_gep_reduce_ex", "hs_gep_workspace_bytes",
+                 "hs_gep_check_schedule"):
         assert want in names
 
 
