@@ -884,30 +884,37 @@ hipStream_t aux_stream(int which) {
 // Cholesky, right-looking over panels of LB columns: factor and invert the
 // diagonal block, then the panel L21 = S21 L11^{-H} (as LH21 = M11 S21^H) and
 // the update of the trailing lower triangle S22 -= L21 L21^H.
-// Lookahead (from 4 panels on), with three streams:
-//   caller's    leaf, panel product, update of the next column block;
-//   lookahead   L21 = LH21^H (an output only), then the bulk of the update,
-//               beside the next leaf and panel;
+// Lookahead (from 4 panels on), with three streams and panels in pairs:
+//   caller's    leaf, panel product; after the first panel of a pair the
+//               update of the next column block with it, after the second
+//               the update of the next two column blocks with both panels
+//               (contraction 2 LB);
+//   lookahead   L21 = LH21^H (an output only); after the second panel of a
+//               pair the bulk of the update with both panels (contraction
+//               2 LB), beside the next two leaves and panels;
 //   transposes  the next panel's S21^H, beside the next leaf.
-// The next column block's update waits for the previous bulk update (both
-// write that block); the bulk update and L21 wait for the panel they use;
-// the next S21^H waits for the next column block's update.
+// The update of the two column blocks after a pair waits for the previous
+// pair's bulk update (both write those blocks); the bulk update and L21
+// wait for the panel they use; the next S21^H waits for the update of its
+// column block.
 template <class Hook>
 hipError_t factor(const Gep &g, Hook after_panel) {
     const int N = g.N;
     const int np = (N + LB - 1) / LB;
     Gep ga = g, gc = g;
-    hipEvent_t e_panel = nullptr, e_bulk = nullptr, e_next = nullptr, e_w = nullptr;
+    hipEvent_t e_panel = nullptr, e_bulk = nullptr, e_look = nullptr, e_next = nullptr,
+               e_w = nullptr;
     bool ahead = np >= 4;
     if (ahead) {
         ga.st = aux_stream(0);
         gc.st = aux_stream(2);
         ahead = ga.st != nullptr && gc.st != nullptr && ev_create(&e_panel) == hipSuccess &&
-                ev_create(&e_bulk) == hipSuccess && ev_create(&e_next) == hipSuccess &&
-                ev_create(&e_w) == hipSuccess;
+                ev_create(&e_bulk) == hipSuccess && ev_create(&e_look) == hipSuccess &&
+                ev_create(&e_next) == hipSuccess && ev_create(&e_w) == hipSuccess;
     }
-    // recorded events still to be waited for (no wait on an unrecorded event)
-    bool bulk_pending = false, w_pending = false;
+    // recorded events still to be waited for (no wait on an unrecorded event);
+    // e_bulk: the last bulk update, e_look: everything on the lookahead stream
+    bool bulk_pending = false, look_pending = false, w_pending = false;
     hipError_t err = hipSuccess;
     // S21^H of the first panel, beside the first leaf
     const auto next_s21h = [&](int c0, int c1) -> hipError_t {   // columns [c0, c1)
@@ -950,31 +957,40 @@ hipError_t factor(const Gep &g, Hook after_panel) {
             break;                                                                 // LH21 = M11 S21^H
         // the hook also gets the lookahead stream's latest event (or null),
         // which orders that stream's pending work before anything it forks
-        if ((err = after_panel(t0, bulk_pending ? e_bulk : nullptr)) != hipSuccess) break;
+        if ((err = after_panel(t0, look_pending ? e_look : nullptr)) != hipSuccess) break;
+        const bool second = ((kb / LB) & 1) != 0;   // second panel of a pair
+        const int k0 = second ? kb - LB : kb;        // first contraction row of the update
         const int t1 = N - t0 < LB ? N : t0 + LB;
+        const int u1 = second ? std::min(N, t0 + 2 * LB) : t1;   // columns the caller updates
         if ((err = ev_record(e_panel, g.st)) != hipSuccess) break;
-        if (bulk_pending && (err = ev_wait(g.st, e_bulk, WT_BLOCK_AFTER_BULK)) != hipSuccess) break;
+        if (second && bulk_pending &&
+            (err = ev_wait(g.st, e_bulk, WT_BLOCK_AFTER_BULK)) != hipSuccess)
+            break;
         if ((err = ev_wait(ga.st, e_panel, WT_AHEAD_AFTER_PANEL)) != hipSuccess) break;
         if ((err = conj_t(ga, g.LH, g.L, kb, t0, t0, N)) != hipSuccess) break;    // L21
-        if (t1 < N && (err = mm(ga, g.LH, g.LH, g.L, t1, N, t1, N, kb, t0, MM_LOWER, OP_SUB)) !=
-                          hipSuccess)
-            break;                                                                 // the rest
-        if ((err = ev_record(e_bulk, ga.st)) != hipSuccess) break;
-        bulk_pending = true;
-        if ((err = mm(g, g.LH, g.LH, g.L, t0, N, t0, t1, kb, t0, MM_MASK, OP_SUB)) != hipSuccess)
-            break;                                                                 // next column block
+        if (second) {
+            if (u1 < N && (err = mm(ga, g.LH, g.LH, g.L, u1, N, u1, N, k0, t0, MM_LOWER,
+                                    OP_SUB)) != hipSuccess)
+                break;                                                             // the rest
+            if ((err = ev_record(e_bulk, ga.st)) != hipSuccess) break;
+            bulk_pending = true;
+        }
+        if ((err = ev_record(e_look, ga.st)) != hipSuccess) break;
+        look_pending = true;
+        if ((err = mm(g, g.LH, g.LH, g.L, t0, N, t0, u1, k0, t0, MM_MASK, OP_SUB)) != hipSuccess)
+            break;                                                                 // next column block(s)
         if (t1 < N) err = next_s21h(t0, t1);
     }
     // join the other streams, also after an error
-    if (bulk_pending) {
-        const hipError_t e = ev_wait(g.st, e_bulk, WT_JOIN_AHEAD);
+    if (look_pending) {
+        const hipError_t e = ev_wait(g.st, e_look, WT_JOIN_AHEAD);
         if (err == hipSuccess) err = e;
     }
     if (w_pending) {
         const hipError_t e = ev_wait(g.st, e_w, WT_JOIN_TRANSPOSE);
         if (err == hipSuccess) err = e;
     }
-    for (hipEvent_t e : {e_panel, e_bulk, e_next, e_w}) ev_destroy(e);
+    for (hipEvent_t e : {e_panel, e_bulk, e_look, e_next, e_w}) ev_destroy(e);
     return err;
 }
 
