@@ -89,8 +89,9 @@ def test_two_term_form_against_the_oracle():
     _check(H, S, *_gep_gpu(H, S))
 
 
+@pytest.mark.parametrize("mode", [0, 3])
 @pytest.mark.parametrize("cond", [1e4, 1e8])
-def test_ill_conditioned_overlap(cond):
+def test_ill_conditioned_overlap(cond, mode):
     """S with singular values spread over [1/cond, 1] (the paper's overlaps are
     positive definite up to a few very small singular values). Two correct
     FP64 orders of the reduction differ in Ht by about cond(S) u (u = 2^-53)
@@ -107,13 +108,14 @@ def test_ill_conditioned_overlap(cond):
     S = 0.5 * (S + S.conj().T)
     B = cn(rng, (N, N))
     H = B + B.conj().T
-    L, Ht, info = _gep_gpu(H, S)
+    L, Ht, info = _gep_gpu(H, S, mode=mode)
     L0, Ht0, inf0 = O.gep_reduce(H, S)
     assert info == 0 and inf0 == 0
     eL, eH = _rel(L, L0), _rel(Ht, Ht0)
     rS = np.linalg.norm(L @ L.conj().T - S) / np.linalg.norm(S)
     rH = np.linalg.norm(L @ Ht @ L.conj().T - H) / np.linalg.norm(H)
-    print(f"  cond {cond:.0e}: L {eL:.2e} Ht {eH:.2e} res S {rS:.2e} res H {rH:.2e}", flush=True)
+    print(f"  cond {cond:.0e} mode {mode}: L {eL:.2e} Ht {eH:.2e} res S {rS:.2e} res H {rH:.2e}",
+          flush=True)
     assert eL <= 10 * N * np.sqrt(cond) * u
     assert eH <= 10 * cond * u
     assert rS <= 1e-13
@@ -339,7 +341,7 @@ def test_largest_size_residuals():
 # 3M products change only the rounding (the imaginary parts' bound grows by a
 # small constant factor), so the same bars hold.
 
-@pytest.mark.parametrize("N", [65, 300, 1100, 4200])
+@pytest.mark.parametrize("N", [1, 2, 65, 129, 300, 1100, 4200])
 def test_3m_random_pairs(N):
     from paper_1611_00606_amd import HS_FP64_3M
     H, S = _random_pair(N, seed=700 + N)
