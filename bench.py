@@ -259,11 +259,11 @@ SPLIT_MODES = {
 
 def split_bench(p, steps: int, warmup: int, fp64_ms: float, hip, mode: int, n_cols: int = 12,
                 atom_kw=None):
-    """Split-precision (or 3M) form on the same workload: time, speedup over
-    the FP64 path, and relative Frobenius error of H and of S against the CPU
-    oracle on sampled columns."""
+    """Split-precision (or 3M) form on the same workload: time and speedup
+    over the FP64 path. Returns (result, sample): the sample holds seeded
+    columns of its H and S, which the CPU-baseline leg compares with the
+    oracle (cpu_baseline_errors)."""
     import torch
-    import oracle
     from paper_1611_00606_amd import DeviceBuild
     from paper_1611_00606_amd.flops import algorithmic_flops, reduction_flops
 
@@ -278,8 +278,6 @@ def split_bench(p, steps: int, warmup: int, fp64_ms: float, hip, mode: int, n_co
     Sc = run.S.index_select(1, idx).cpu().numpy()
     del run
     torch.cuda.empty_cache()
-    Hr = oracle.hamiltonian_columns(p.A, p.B, p.T_AA, p.T_AB, p.T_BB, p.nl, cols)
-    Sr = oracle.overlap_columns(p.A, p.B, p.U, p.nl, cols)
     f = algorithmic_flops(p.nl, p.N_G, info)
     issued = m["per_fp64"] * reduction_flops(p.nl, p.N_G) / (ph[2] * 1e-3) / 1e12
     return {
@@ -298,10 +296,27 @@ def split_bench(p, steps: int, warmup: int, fp64_ms: float, hip, mode: int, n_co
             "unit": m["unit"],
             "frac": round(issued / m["peak"], 4),
         },
-        "rel_err_H": float(np.linalg.norm(Hc - Hr) / np.linalg.norm(Hr)),
-        "rel_err_S": float(np.linalg.norm(Sc - Sr) / np.linalg.norm(Sr)),
-        "err_sample": f"{len(cols)} seeded columns of H and S vs the CPU oracle",
-    }
+        "rel_err_H": None,
+        "rel_err_S": None,
+        "err_sample": f"{len(cols)} seeded columns of H and S vs the CPU oracle "
+                      "(evaluated in the CPU-baseline leg; null with --no-cpu-baseline)",
+    }, (cols, Hc, Sc)
+
+
+def cpu_baseline_errors(p, samples):
+    """CPU-baseline leg: the oracle's columns of H and S for the columns each
+    GPU form sampled, and each form's relative Frobenius error on them."""
+    import oracle
+    cache, out = {}, {}
+    for name, (cols, Hc, Sc) in samples.items():
+        key = tuple(int(c) for c in cols)
+        if key not in cache:
+            cache[key] = (oracle.hamiltonian_columns(p.A, p.B, p.T_AA, p.T_AB, p.T_BB, p.nl, cols),
+                          oracle.overlap_columns(p.A, p.B, p.U, p.nl, cols))
+        Hr, Sr = cache[key]
+        out[name] = (float(np.linalg.norm(Hc - Hr) / np.linalg.norm(Hr)),
+                     float(np.linalg.norm(Sc - Sr) / np.linalg.norm(Sr)))
+    return out
 
 
 def batching_bench(seed: int, steps: int, hip):
@@ -424,7 +439,7 @@ def serving_bench(seed: int, n_slots: int = 4, arena_gb: float = 24.0, n_sets: i
 
 def gep_bench(run, steps: int, hip):
     """Reduction of the generalized eigenproblem (S = L L^H, Ht = L^-1 H L^-H)
-    applied to the H and S this build produced, timed with HIP events on the
+    applied to the H and S the timed build produced, timed with HIP events on the
     launch stream; then the same with the products in the 3M form."""
     import torch
     from paper_1611_00606_amd import HS_FP64, HS_FP64_3M, hs_gep_reduce, hs_gep_workspace_bytes
@@ -647,17 +662,21 @@ def main():
     del run
     torch.cuda.empty_cache()
     out["hs_build_sync_wall_ms"] = sync_build_wall_ms(p)
+    samples = {}   # GPU columns of the alternative forms, checked in the CPU-baseline leg
     if not args.no_split:
         print("bench: split precision and 3M", file=sys.stderr, flush=True)
         hip = HipEvents()
         for mode in [int(m) for m in args.split_modes.split(",") if m]:
-            out[SPLIT_MODES[mode]["name"]] = split_bench(p, max(3, args.steps // 2), 1, ms_step,
-                                                         hip, mode, atom_kw=atom_kw)
+            name = SPLIT_MODES[mode]["name"]
+            out[name], samples[name] = split_bench(p, max(3, args.steps // 2), 1, ms_step, hip,
+                                                   mode, atom_kw=atom_kw)
     if not args.no_batching:
         print("bench: batched per-atom stage", file=sys.stderr, flush=True)
         out["batching"] = batching_bench(args.seed, max(3, args.steps // 2), HipEvents())
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+        for name, (eh, es) in cpu_baseline_errors(p, samples).items():
+            out[name]["rel_err_H"], out[name]["rel_err_S"] = eh, es
         if "gep" in out:
             out["gep"]["cpu_baseline"] = cpu_baseline_gep(out["gep"]["N"])
     if not args.no_serving:
