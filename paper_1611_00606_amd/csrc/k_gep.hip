@@ -225,10 +225,12 @@ __global__ void __launch_bounds__(MmCfg::NT) k_gep_mm(const MmArgs args) {
 // MFMA fragment loads and the accumulator stores hit distinct banks).
 //   factor, right-looking over 16-column panels P:
 //     wave 0: Cholesky of the diagonal tile in registers (lane r holds row
-//             r; values broadcast with readlane);
+//             r; values broadcast with readlane), for P > 0 right after its
+//             own update of that tile in the previous panel's trailing step;
 //     panel:  L_IP = C_IP L_PP^{-H}            by substitution, one thread
 //             per row of the panel;
-//     update: C_IJ -= L_IP L_JP^H, P < J <= I   tiles spread over the waves.
+//     update: C_IJ -= L_IP L_JP^H, P < J <= I   tiles spread over waves
+//             1..7 (wave 0 takes tile (P+1, P+1), then factors it).
 //   inverse X = L^{-1}, in place: every wave inverts one diagonal tile, then
 //     for block rows I = 1..7: X_IJ = -X_II sum_{J<=K<I} L_IK X_KJ, J < I.
 // A pivot that is not > 0 (NaN included) records kb + j + 1 in *info unless an
@@ -359,21 +361,39 @@ k_gep_leaf(double2 *__restrict__ L, double2 *__restrict__ M, double2 *__restrict
     __syncthreads();
 
     int inf = 0;
-    for (int P = 0; P < LT; ++P) {
-        if (w == 0) {
-            double2 *D = ltile(T, P, P);
-            double2 a[16];
-            const int r = lane & 15;
+    // Cholesky of diagonal tile P by wave 0
+    const auto diag = [&](int P) {
+        double2 *D = ltile(T, P, P);
+        double2 a[16];
+        const int r = lane & 15;
 #pragma unroll
-            for (int k = 0; k < 16; ++k) a[k] = D[lsw(r, k)];
-            const int f = chol16(a, lane);
-            if (f != 0 && inf == 0 && 16 * P + f <= nb) inf = 16 * P + f;
-            if (lane < 16) {
+        for (int k = 0; k < 16; ++k) a[k] = D[lsw(r, k)];
+        const int f = chol16(a, lane);
+        if (f != 0 && inf == 0 && 16 * P + f <= nb) inf = 16 * P + f;
+        if (lane < 16) {
 #pragma unroll
-                for (int k = 0; k < 16; ++k) D[lsw(lane, k)] = a[k];
-            }
+            for (int k = 0; k < 16; ++k) D[lsw(lane, k)] = a[k];
         }
-        __syncthreads();
+    };
+    // C_IJ -= L_IP L_JP^H for the t-th tile of the trailing triangle of panel P
+    const auto trail = [&](int P, int t) {
+        int ti, tj;
+        tri_decode(t, ti, tj);
+        const int I = P + 1 + ti, J = P + 1 + tj;
+        Cacc c;
+        acc_zero(c);
+        mma_abh(c, ltile(T, I, P), ltile(T, J, P), lane);
+        double2 *C = ltile(T, I, J);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            double2 &o = C[lsw(4 * v + (lane >> 4), lane & 15)];
+            o.x -= c.re[v];
+            o.y -= c.im[v];
+        }
+    };
+    if (w == 0) diag(0);
+    __syncthreads();
+    for (int P = 0; P < LT; ++P) {
         // panel: row r of L_IP solves x L_PP^H = C_IP[r] by substitution,
         // x_j = (c_j - sum_{k<j} x_k conj(l_jk)) / l_jj, one thread per row
         if (tid < (LT - 1 - P) * 16) {
@@ -401,22 +421,17 @@ k_gep_leaf(double2 *__restrict__ L, double2 *__restrict__ M, double2 *__restrict
             for (int k = 0; k < 16; ++k) C[lsw(rr, k)] = x[k];
         }
         __syncthreads();
-        // trailing lower triangle: C_IJ -= L_IP L_JP^H
+        // trailing lower triangle: wave 0 updates the next diagonal tile
+        // (t = 0) and factors it at once, beside the other waves' updates
         const int n = LT - 1 - P;
-        for (int t = w; t < n * (n + 1) / 2; t += 8) {
-            int ti, tj;
-            tri_decode(t, ti, tj);
-            const int I = P + 1 + ti, J = P + 1 + tj;
-            Cacc c;
-            acc_zero(c);
-            mma_abh(c, ltile(T, I, P), ltile(T, J, P), lane);
-            double2 *C = ltile(T, I, J);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                double2 &o = C[lsw(4 * v + (lane >> 4), lane & 15)];
-                o.x -= c.re[v];
-                o.y -= c.im[v];
+        if (w == 0) {
+            if (n > 0) {
+                trail(P, 0);
+                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+                diag(P + 1);
             }
+        } else {
+            for (int t = w; t < n * (n + 1) / 2; t += 7) trail(P, t);
         }
         __syncthreads();
     }
