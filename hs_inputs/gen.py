@@ -11,7 +11,9 @@ depend on the order in which the others are drawn):
   * T_AA,a         herm(M M^H / N_L + I), M ~ CN(0,1)^{N_L x N_L}
   * T_AB,a         CN(0,1)/N_L
   * T_BB,a         (X + X^H) / (2 N_L),   X ~ CN(0,1)^{N_L x N_L}
-  * U_a            real uniform [0.5, 2] stored as complex
+  * U_a            real uniform [0.5, 2] stored as complex; with complex_u,
+                   the same moduli times e^{i phi}, phi uniform in [0, 2 pi)
+                   (its own child stream), so |u|^2 differs from Re(u)^2
   * failing atoms  T_AA,a <- T_AA,a - 2 lambda_max(T_AA,a) I (fails at pivot 1)
 where herm(T) = (T + T^H)/2, which is exactly Hermitian in IEEE arithmetic
 (the diagonal's imaginary part is exactly zero and mirrored entries are exact
@@ -29,7 +31,7 @@ from typing import Dict, List, Optional, Sequence
 import numpy as np
 
 # Named child streams, in a fixed order.
-_STREAMS = ("A", "B", "T_AA", "T_AB", "T_BB", "U", "fail", "plant")
+_STREAMS = ("A", "B", "T_AA", "T_AB", "T_BB", "U", "fail", "plant", "U_phase")
 
 
 def cn(rng: np.random.Generator, shape) -> np.ndarray:
@@ -128,13 +130,15 @@ def make_problem(
     fail_atoms: Optional[Sequence[int]] = None,
     planted: Optional[Dict[int, int]] = None,
     name: str = "custom",
+    complex_u: bool = False,
 ) -> Problem:
     """Draw one problem.
 
     N_L is an int (all atoms alike) or a sequence of N_A ints (mixed types).
     n_fail atoms (seeded choice without replacement), or the explicit
     fail_atoms, get the -2 lambda_max shift. `planted` maps atom -> 1-based
-    pivot at which that atom's T_AA is built to fail.
+    pivot at which that atom's T_AA is built to fail. complex_u gives every
+    U entry a seeded phase (the moduli are the same draws as without it).
     """
     if np.isscalar(N_L):
         nl = np.full(N_A, int(N_L), dtype=np.int32)
@@ -159,6 +163,8 @@ def make_problem(
         x = cn(rng["T_BB"], (n, n))
         t_bb.append(((x + x.conj().T) / (2 * n)).reshape(-1))
     U = rng["U"].uniform(0.5, 2.0, size=K).astype(np.complex128)
+    if complex_u:
+        U *= np.exp(1j * rng["U_phase"].uniform(0.0, 2.0 * np.pi, size=K))
 
     prob = Problem(
         A=A, B=B,
@@ -192,6 +198,10 @@ CONFIGS = {
     # four atom types of different l_max, 5% of atoms failing (round(6.4) = 6)
     "batching": dict(N_A=128, N_L=[16] * 32 + [49] * 32 + [81] * 32 + [121] * 32,
                      N_G=6000, n_fail=6),
+    # the paper's two test systems at K_max = 4.0 (Tab. 1), synthetic values of
+    # the same shapes: NaCl (512 atoms, l_max 6) and AuAg (108 atoms, l_max 10)
+    "nacl_kmax4": dict(N_A=512, N_L=49, N_G=9273, n_fail=0),
+    "auag_kmax4": dict(N_A=108, N_L=121, N_G=13379, n_fail=0),
 }
 
 # Serving workload: one resident atom set, a stream of k-point requests.

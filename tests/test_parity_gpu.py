@@ -1,9 +1,11 @@
 """Parity of the HIP path (through the C ABI) with the CPU oracle.
 
 Small and medium cases compare every element (relative Frobenius error of H
-and S <= 1e-12, the FP64 bound); the large workloads, in the launch
-configuration the benchmark times, compare sampled columns computed one by
-one by the oracle and bilinear probes. The Cholesky flags are integer
+and S <= 1e-12, the FP64 bound); the large workloads, built here with
+separate per-atom launches (batch = 0), compare sampled columns computed one
+by one by the oracle and bilinear probes. The launch configuration the
+benchmark times (batched per-atom stage, autotuned tile shapes) is checked
+the same way in test_bench_config_gpu.py. The Cholesky flags are integer
 decisions and must match exactly (inputs are built with a clear margin).
 """
 

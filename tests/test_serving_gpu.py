@@ -5,7 +5,11 @@
 * every request's H and S are the same alone and in a mix of concurrently
   admitted requests (bitwise: the kernels are deterministic);
 * the arena never holds more than its budget while requests are admitted;
-* served results match the CPU oracle.
+* served results match the CPU oracle;
+* on the serving workload's own atom set (64 atoms, N_L = 64) and request
+  sizes (N_G 1500..9000, fresh A, B per request), in all four reduction
+  modes: every request alone against the oracle (sampled columns, bilinear
+  probe), and bitwise the same result in a contended mix.
 """
 
 import ctypes
@@ -15,6 +19,7 @@ import pytest
 
 import oracle as O
 from hs_inputs import make_problem
+from _parity import MODE_NAME, MODE_TOL, check_columns_and_probes, rel, sample_columns
 
 pytestmark = pytest.mark.gpu
 
@@ -141,3 +146,123 @@ def test_oversized_request_is_rejected(atoms, ctx):
         hs_server_submit(srv, 1, 200, buf.ctypes.data, buf.ctypes.data, 200)
     assert e.value.status == 3
     hs_server_destroy(srv)
+
+
+# --------------------------------------------------------------------------
+# The serving workload itself: 64 atoms of N_L = 64 resident, requests with
+# fresh seeded A, B and N_G from 1500 to 9000, in every reduction mode.
+# --------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def c5_atoms():
+    from hs_inputs import serving_atoms
+    return serving_atoms(0)
+
+
+@pytest.fixture(scope="module")
+def c5_ctx(c5_atoms):
+    from paper_1611_00606_amd.serving import Context
+    a = c5_atoms
+    c = Context(a.T_AA, a.T_AB, a.T_BB, a.U, a.nl)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def c5_requests(c5_atoms):
+    """Eight requests: the smallest and largest N_G of the range and the first
+    six sizes of the seeded stream, each with its own A, B (pinned host)."""
+    from concurrent.futures import ThreadPoolExecutor
+    from hs_inputs import serving_request_ab, serving_requests
+    sizes = [1500, 9000] + [int(x) for x in serving_requests(0)[:6]]
+    K = c5_atoms.K
+
+    def one(r):
+        A, Bm = serving_request_ab(0, r, sizes[r], K)
+        return sizes[r], _pinned(A), _pinned(Bm)
+
+    with ThreadPoolExecutor(4) as ex:
+        return list(ex.map(one, range(len(sizes))))
+
+
+def _serve_mode(ctx, reqs, arrivals, n_slots, arena, mode, on_host):
+    """Serve pinned requests [(N_G, A, B)] in `mode`; on_host(i, H, S) gets
+    host copies of every result."""
+    from paper_1611_00606_amd.serving import ServingLoop, device_matrix_to_host
+    rq = [{"id": i, "N_G": n_g, "A_ptr": A.data_ptr(), "B_ptr": Bm.data_ptr(), "ld": n_g}
+          for i, (n_g, A, Bm) in enumerate(reqs)]
+
+    def on_result(res):
+        n = res["N_G"]
+        on_host(res["id"], device_matrix_to_host(res["H"], n), device_matrix_to_host(res["S"], n))
+
+    loop = ServingLoop(ctx, n_slots, arena, mode=mode)
+    recs = loop.run(rq, arrivals, on_result=on_result)
+    peak = loop.peak_bytes
+    loop.close()
+    return recs, peak
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2, 3], ids=lambda m: MODE_NAME[m])
+def test_serving_workload_alone_equals_mix_and_oracle(c5_atoms, c5_ctx, c5_requests, mode):
+    """Each request alone (one slot, nothing else in flight): sampled columns
+    and bilinear probes against the oracle. Then all eight arrive at once on
+    three slots with an arena that holds about three of them: the arena
+    stays within its budget, requests overlap and queue, and every result is
+    bitwise the one served alone."""
+    a, ctx, reqs = c5_atoms, c5_ctx, c5_requests
+    tol = MODE_TOL[mode]
+    alone = {}
+    for i, (n_g, A, Bm) in enumerate(reqs):
+        print(f"case serving request {i} N_G={n_g} mode={MODE_NAME[mode]} alone", flush=True)
+
+        def keep(_, H, S, i=i):
+            alone[i] = (H, S)
+
+        _serve_mode(ctx, [reqs[i]], [0.0], 1, ctx.footprint_bytes(n_g, mode), mode, keep)
+        H, S = alone[i]
+        cols = sample_columns(n_g, seed=i, n_random=2)
+        check_columns_and_probes(A.numpy(), Bm.numpy(), a.T_AA, a.T_AB, a.T_BB, a.U, a.nl,
+                                 H, S, cols, tol, n_probe=1, probe_seed=i)
+    arena = int(3.2 * max(ctx.footprint_bytes(n, mode) for n, _, _ in reqs))
+    same = {}
+
+    def compare(i, H, S):
+        same[i] = bool(np.array_equal(H, alone[i][0]) and np.array_equal(S, alone[i][1]))
+
+    print(f"case serving mix of {len(reqs)} mode={MODE_NAME[mode]}", flush=True)
+    recs, peak = _serve_mode(ctx, reqs, [0.0] * len(reqs), 3, arena, mode, compare)
+    assert peak <= arena
+    assert len(recs) == len(reqs)
+    overl = sum(1 for x in recs for y in recs if x["id"] < y["id"]
+                and x["admit"] < y["done"] and y["admit"] < x["done"])
+    assert overl >= 1
+    assert max(r["admit"] - r["submit"] for r in recs) > 0.0   # someone queued
+    assert all(same[i] for i in range(len(reqs))), same
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2, 3], ids=lambda m: MODE_NAME[m])
+def test_context_complex_u_matches_oracle(mode):
+    """The resident context keeps |u|^2 of a complex U (its S matches the oracle)."""
+    from paper_1611_00606_amd.serving import Context
+    torch = _torch()
+    atoms = make_problem(4, [16, 49, 25, 64], 1, seed=51, fail_atoms=[1], complex_u=True)
+    q = make_problem(atoms.N_A, atoms.nl, 411, seed=52)
+    ctx = Context(atoms.T_AA, atoms.T_AB, atoms.T_BB, atoms.U, atoms.nl)
+    try:
+        dev = torch.device("cuda:0")
+        A = torch.from_numpy(q.A).to(dev)
+        Bm = torch.from_numpy(q.B).to(dev)
+        H = torch.empty((q.N_G, q.N_G), dtype=torch.complex128, device=dev)
+        S = torch.empty_like(H)
+        ws = torch.empty(ctx.workspace_bytes(q.N_G, mode), dtype=torch.uint8, device=dev)
+        ctx.build(A, Bm, q.N_G, H, S, ws, mode=mode)
+        torch.cuda.synchronize()
+        Hr = O.hamiltonian(q.A, q.B, atoms.T_AA, atoms.T_AB, atoms.T_BB, atoms.nl)
+        Sr = O.overlap(q.A, q.B, atoms.U, atoms.nl)
+        eh = rel(H.cpu().numpy(), Hr)
+        es = rel(S.cpu().numpy(), Sr)
+        print(f"  context complex U mode={MODE_NAME[mode]} rel err H {eh:.2e} S {es:.2e}", flush=True)
+        assert eh <= MODE_TOL[mode] and es <= MODE_TOL[mode]
+    finally:
+        ctx.close()
