@@ -1,22 +1,22 @@
-"""Alg. 1 of the paper on the host, through SciPy's BLAS/LAPACK.
+"""H and S through the factored identities of Sec. 2, on the host with SciPy's
+BLAS/LAPACK.
 
-TEST INFRASTRUCTURE ONLY (same rules as hs_oracle): used to pin the direct
-oracle with a second, independent derivation of H and S, and as the
-"CPU only" reference method the paper's tables compare against.
+TEST INFRASTRUCTURE ONLY (same rules as hs_oracle): a second derivation of H
+and S that pins the direct oracle, and the host-side analogue of the paper's
+CPU-only method (its Alg. 1 reaches H and S through the same identities).
 
-Follows Alg. 1 step by step, with the library routine the paper names for
-each step:
-  first loop   Z_a = T^BA_a A_a (zgemm) ; Z_a += 1/2 T^BB_a B_a (zhemm)
-               H = Z^H B + B^H Z (zher2k)
-  S            S = A^H A (zherk) ; B' = U B (scaling) ; S += B'^H B' (zherk)
-  second loop  C_a = Cholesky(T^AA_a) (zpotrf)
-               success: Y_a = C_a^H A_a (ztrmm), stacked into Y_HPD
-               failure: X_a = T^AA_a A_a (zhemm), stacked into X_notHPD,
-                        A_a stacked into A_notHPD
-               H += A_notHPD^H X_notHPD (zgemm) ; H += Y_HPD^H Y_HPD (zherk)
-The Hermitian routines fill the lower triangle; the result is completed by
-conjugate mirroring. Inputs are not modified (the paper's backup/restore of
-A and B is therefore unnecessary).
+Derivation, one output term at a time (Sec. 2):
+  * S is the Gram matrix of the rows of all atoms' A_a and U_a B_a stacked
+    into one matrix G: S = G^H G, a single Hermitian rank-k update.
+  * The cross and B-B terms of H, A^H T^AB B + B^H T^BA A + B^H T^BB B with
+    T^BA = (T^AB)^H, equal Z^H B + B^H Z for Z = T^BA A + 1/2 T^BB B (atom by
+    atom), a single Hermitian rank-2k update over the stacked rows.
+  * The A-A term A_a^H T^AA_a A_a: where T^AA_a = C_a C_a^H has a Cholesky
+    factor (lower C_a), it is (C_a^H A_a)^H (C_a^H A_a), a Hermitian rank-k
+    update of the triangular products; where it has none (the failure case
+    the paper describes), the general product A_a^H (T^AA_a A_a).
+Only lower triangles are accumulated; the result is mirrored at the end.
+Inputs are not modified.
 """
 
 from __future__ import annotations
@@ -25,7 +25,7 @@ import numpy as np
 from scipy.linalg import blas, lapack
 
 
-def _mirror_lower(C):
+def _hermitian_from_lower(C):
     """Full Hermitian matrix from its lower triangle (diagonal imaginary part 0)."""
     L = np.tril(C, -1)
     out = L + L.conj().T
@@ -33,54 +33,69 @@ def _mirror_lower(C):
     return out
 
 
-def algorithm1(A, B, T_AA, T_AB, T_BB, U, nl):
-    """Returns (H, S, info) computed by the steps of Alg. 1."""
+def _hermitian_block(t):
+    """The Hermitian matrix a zhemm/zpotrf reader sees in t: its lower
+    triangle, mirrored, with the diagonal's imaginary part dropped."""
+    full = np.tril(t) + np.tril(t, -1).conj().T
+    full[np.diag_indices(t.shape[0])] = t.diagonal().real
+    return full
+
+
+def _atom_slices(nl):
     nl = np.asarray(nl, dtype=np.int64)
     rows = np.concatenate([[0], np.cumsum(nl)])
     toff = np.concatenate([[0], np.cumsum(nl * nl)])
+    for a, n in enumerate(nl):
+        yield a, slice(rows[a], rows[a + 1]), slice(toff[a], toff[a + 1]), int(n)
+
+
+def _gram_lower(G, C=None):
+    """lower(C + G^H G) by zherk (C None: zero)."""
+    G = np.asfortranarray(G)
+    if C is None:
+        return blas.zherk(1.0, G, trans=2, lower=1)
+    return blas.zherk(1.0, G, beta=1.0, c=np.asfortranarray(C), trans=2, lower=1)
+
+
+def overlap_factored(A, B, U, nl):
+    """S = G^H G with G = [A; U B] (rows of every atom stacked)."""
+    G = np.concatenate([A, U[:, None] * B])
+    return _hermitian_from_lower(_gram_lower(G))
+
+
+def hamiltonian_factored(A, B, T_AA, T_AB, T_BB, nl):
+    """H by its factored terms; returns (H, info) with info[a] the Cholesky
+    status of T^AA_a (0, or LAPACK's first failing pivot)."""
     n_g = A.shape[1]
-
-    def blk(T, a):
-        n = int(nl[a])
-        return np.asfortranarray(T[toff[a]:toff[a + 1]].reshape(n, n))
-
-    # First part of H
+    n_atoms = len(nl)
+    # cross and B-B terms: Z^H B + B^H Z, Z = T^BA A + 1/2 T^BB B per atom
     Z = np.empty_like(A)
-    for a in range(len(nl)):
-        rs = slice(rows[a], rows[a + 1])
-        Aa, Ba = np.asfortranarray(A[rs]), np.asfortranarray(B[rs])
-        tba = np.asfortranarray(blk(T_AB, a).conj().T)
-        za = blas.zgemm(1.0, tba, Aa)
-        za = blas.zhemm(0.5, blk(T_BB, a), Ba, beta=1.0, c=za, side=0, lower=1)
-        Z[rs] = za
+    for _, rs, ts, n in _atom_slices(nl):
+        t_ba = T_AB[ts].reshape(n, n).conj().T
+        t_bb = T_BB[ts].reshape(n, n)
+        Z[rs] = t_ba @ A[rs] + 0.5 * (_hermitian_block(t_bb) @ B[rs])
     H = blas.zher2k(1.0, np.asfortranarray(Z), np.asfortranarray(B), trans=2, lower=1)
-
-    # S
-    S = blas.zherk(1.0, np.asfortranarray(A), trans=2, lower=1)
-    Bu = U[:, None] * B
-    S = blas.zherk(1.0, np.asfortranarray(Bu), beta=1.0, c=S, trans=2, lower=1)
-
-    # Second part of H
-    info = np.zeros(len(nl), dtype=np.int32)
-    Y, X, An = [], [], []
-    for a in range(len(nl)):
-        rs = slice(rows[a], rows[a + 1])
+    # A-A term: triangular factors where they exist, general products elsewhere
+    info = np.zeros(n_atoms, dtype=np.int32)
+    factored, unfactored = [], None
+    for a, rs, ts, n in _atom_slices(nl):
+        t_aa = np.asfortranarray(T_AA[ts].reshape(n, n))
+        c, info[a] = lapack.zpotrf(t_aa, lower=1)
         Aa = np.asfortranarray(A[rs])
-        taa = blk(T_AA, a)
-        c, inf = lapack.zpotrf(taa, lower=1)
-        info[a] = inf
-        if inf == 0:
-            Y.append(blas.ztrmm(1.0, c, Aa, side=0, lower=1, trans_a=2, diag=0))
+        if info[a] == 0:
+            factored.append(blas.ztrmm(1.0, c, Aa, side=0, lower=1, trans_a=2))
         else:
-            X.append(blas.zhemm(1.0, taa, Aa, side=0, lower=1))
-            An.append(Aa)
-    if X:
-        Xs = np.asfortranarray(np.concatenate(X))
-        As = np.asfortranarray(np.concatenate(An))
-        H = H + np.tril(blas.zgemm(1.0, As, Xs, trans_a=2))
-    if Y:
-        Ys = np.asfortranarray(np.concatenate(Y))
-        H = blas.zherk(1.0, Ys, beta=1.0, c=np.asfortranarray(H), trans=2, lower=1)
-
+            term = Aa.conj().T @ (_hermitian_block(t_aa) @ Aa)
+            unfactored = term if unfactored is None else unfactored + term
+    if factored:
+        H = _gram_lower(np.concatenate(factored), H)
+    if unfactored is not None:
+        H = H + np.tril(unfactored)
     assert H.shape == (n_g, n_g)
-    return _mirror_lower(H), _mirror_lower(S), info
+    return _hermitian_from_lower(H), info
+
+
+def algorithm1(A, B, T_AA, T_AB, T_BB, U, nl):
+    """(H, S, info) through the factored identities (see the module docstring)."""
+    H, info = hamiltonian_factored(A, B, T_AA, T_AB, T_BB, nl)
+    return H, overlap_factored(A, B, U, nl), info

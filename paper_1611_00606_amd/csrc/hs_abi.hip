@@ -24,15 +24,21 @@ namespace hs {
 
 namespace {
 thread_local std::string g_last_error;
+thread_local int g_last_status = HS_OK;   // the status g_last_error explains
 constexpr size_t ALIGN = 256;
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 }  // namespace
 
-void set_error(const std::string &msg) { g_last_error = msg; }
-const std::string &last_error() { return g_last_error; }
+void set_error(int status, const std::string &msg) {
+    g_last_error = msg;
+    g_last_status = status;
+}
+const char *message_for(int status) {
+    return status == g_last_status && !g_last_error.empty() ? g_last_error.c_str() : nullptr;
+}
 
 int hip_fail(hipError_t e, const char *where) {
-    g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+    set_error(HS_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
     return HS_ERR_HIP;
 }
 
@@ -50,9 +56,12 @@ int check_device() {
         e = hipGetDeviceProperties(&prop, dev);
         if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
         ok[dev] = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 0;
-        if (!ok[dev]) g_last_error = std::string("unsupported device ") + prop.gcnArchName;
     }
-    return ok[dev] ? HS_OK : HS_ERR_UNSUPPORTED;
+    if (!ok[dev]) {
+        set_error(HS_ERR_UNSUPPORTED, "unsupported device (the kernels are built for gfx950)");
+        return HS_ERR_UNSUPPORTED;
+    }
+    return HS_OK;
 }
 
 namespace {
@@ -230,7 +239,7 @@ hipError_t enqueue_kpoint(const AtomPlan &p, const AtomBufs &ab, int n_g, int mo
                          ab.sel, stage.info ? stage.info : ab.info, kb.Z, kb.W};
         e = launch_batch(p, ab.atoms(p), bp, n_g, stage.factor, io, kb.batch, st);
     } else {
-        e = launch_atom(ab.atoms(p), n_g, A, B, T_AB, ab.M1, ab.M2, kb.Z, kb.W, st);
+        e = launch_atom(ab.atoms(p), n_g, A, B, T_AB, ab.M1, ab.M2, ab.sel, kb.Z, kb.W, st);
     }
     if (e != hipSuccess) return e;
     if ((e = mark(2)) != hipSuccess) return e;
@@ -266,13 +275,10 @@ hipError_t enqueue_kpoint(const AtomPlan &p, const AtomBufs &ab, int n_g, int mo
     return mark(4);
 }
 
-}  // namespace hs
-
-namespace {
-
-int check_args(const hs_complex *A, const hs_complex *B, const hs_complex *T_AA,
-               const hs_complex *T_AB, const hs_complex *T_BB, const hs_complex *U, int N_A,
-               int N_L, int N_G, const hs_complex *H, const hs_complex *S, bool per_atom) {
+int check_build_args(const hs_complex *A, const hs_complex *B, const hs_complex *T_AA,
+                     const hs_complex *T_AB, const hs_complex *T_BB, const hs_complex *U,
+                     int N_A, int N_L, int N_G, const hs_complex *H, const hs_complex *S,
+                     bool per_atom) {
     if (!A) return -1;
     if (!B) return -2;
     if (!T_AA) return -3;
@@ -287,14 +293,16 @@ int check_args(const hs_complex *A, const hs_complex *B, const hs_complex *T_AA,
     return HS_OK;
 }
 
+namespace {
 const double2 *c2(const hs_complex *x) { return reinterpret_cast<const double2 *>(x); }
 double2 *c2(hs_complex *x) { return reinterpret_cast<double2 *>(x); }
+}  // namespace
 
 // One-shot build: atom part then k-point part of one workspace.
-int run(const hs::AtomPlan &p, int n_g, int mode, const hs_complex *A, const hs_complex *B,
-        const hs_complex *T_AA, const hs_complex *T_AB, const hs_complex *T_BB,
-        const hs_complex *U, hs_complex *H, hs_complex *S, char *ws, int32_t *info_user,
-        hipStream_t st, void **events, bool batch = false, const hs_tuning *tuning = nullptr) {
+int run_build(const AtomPlan &p, int n_g, int mode, const hs_complex *A, const hs_complex *B,
+              const hs_complex *T_AA, const hs_complex *T_AB, const hs_complex *T_BB,
+              const hs_complex *U, hs_complex *H, hs_complex *S, char *ws, int32_t *info_user,
+              hipStream_t st, void **events, bool batch, const hs_tuning *tuning) {
     hipEvent_t ev[HS_NUM_PHASE_EVENTS] = {};
     if (events)
         for (int i = 0; i < HS_NUM_PHASE_EVENTS; ++i) ev[i] = static_cast<hipEvent_t>(events[i]);
@@ -322,7 +330,9 @@ int run(const hs::AtomPlan &p, int n_g, int mode, const hs_complex *A, const hs_
     return HS_OK;
 }
 
-}  // namespace
+}  // namespace hs
+
+using hs::c2;
 
 extern "C" {
 
@@ -337,7 +347,8 @@ int hs_build_ex(const hs_complex *A, const hs_complex *B, const hs_complex *T_AA
                 const hs_complex *T_AB, const hs_complex *T_BB, const hs_complex *U, int N_A,
                 int N_L, int N_G, hs_complex *H, hs_complex *S, const hs_options *opt) {
     if (!opt) return -12;
-    int rc = check_args(A, B, T_AA, T_AB, T_BB, U, N_A, N_L, N_G, H, S, opt->nl_per_atom != nullptr);
+    int rc = hs::check_build_args(A, B, T_AA, T_AB, T_BB, U, N_A, N_L, N_G, H, S,
+                                  opt->nl_per_atom != nullptr);
     if (rc != HS_OK) return rc;
     if (!hs::valid_mode(opt->mode) || (opt->batch != 0 && opt->batch != 1)) return -12;
     hs::AtomPlan p;
@@ -348,9 +359,15 @@ int hs_build_ex(const hs_complex *A, const hs_complex *B, const hs_complex *T_AA
     if (reinterpret_cast<uintptr_t>(opt->workspace) % 16) return -12;   // 16-byte loads
     rc = hs::check_device();
     if (rc != HS_OK) return rc;
-    if (!opt->workspace || opt->workspace_bytes < p.atom_bytes() + p.kpoint_bytes(N_G, opt->mode))
+    const size_t need = p.atom_bytes() + p.kpoint_bytes(N_G, opt->mode);
+    if (!opt->workspace || opt->workspace_bytes < need) {
+        hs::set_error(HS_ERR_WORKSPACE, "workspace too small: the build needs " + std::to_string(need) +
+                      " bytes, " + std::to_string(opt->workspace ? opt->workspace_bytes : 0) +
+                      " given");
         return HS_ERR_WORKSPACE;
-    return run(p, N_G, opt->mode, A, B, T_AA, T_AB, T_BB, U, H, S, static_cast<char *>(opt->workspace),
+    }
+    return hs::run_build(p, N_G, opt->mode, A, B, T_AA, T_AB, T_BB, U, H, S,
+                         static_cast<char *>(opt->workspace),
                opt->info, static_cast<hipStream_t>(opt->stream), opt->phase_events,
                opt->batch != 0, opt->tuning);
 }
@@ -358,7 +375,7 @@ int hs_build_ex(const hs_complex *A, const hs_complex *B, const hs_complex *T_AA
 int hs_build(const hs_complex *A, const hs_complex *B, const hs_complex *T_AA,
              const hs_complex *T_AB, const hs_complex *T_BB, const hs_complex *U, int N_A,
              int N_L, int N_G, hs_complex *H, hs_complex *S) {
-    int rc = check_args(A, B, T_AA, T_AB, T_BB, U, N_A, N_L, N_G, H, S, false);
+    int rc = hs::check_build_args(A, B, T_AA, T_AB, T_BB, U, N_A, N_L, N_G, H, S, false);
     if (rc != HS_OK) return rc;
     hs::AtomPlan p;
     rc = p.make(N_A, nullptr, N_L);
@@ -368,12 +385,12 @@ int hs_build(const hs_complex *A, const hs_complex *B, const hs_complex *T_AA,
     void *ws = nullptr;
     hipError_t e = hipMalloc(&ws, p.atom_bytes() + p.kpoint_bytes(N_G));
     if (e == hipErrorOutOfMemory) {
-        hs::set_error("workspace allocation");
+        hs::set_error(HS_ERR_NOMEM, "workspace allocation");
         return HS_ERR_NOMEM;
     }
     if (e != hipSuccess) return hs::hip_fail(e, "hipMalloc");
-    rc = run(p, N_G, HS_FP64, A, B, T_AA, T_AB, T_BB, U, H, S, static_cast<char *>(ws), nullptr,
-             nullptr, nullptr);
+    rc = hs::run_build(p, N_G, HS_FP64, A, B, T_AA, T_AB, T_BB, U, H, S, static_cast<char *>(ws),
+                       nullptr, nullptr, nullptr, false, nullptr);
     e = hipStreamSynchronize(nullptr);
     if (rc == HS_OK && e != hipSuccess) rc = hs::hip_fail(e, "hs_build execution");
     hipError_t e2 = hipFree(ws);
@@ -402,7 +419,12 @@ int hs_gep_reduce_ex(const hs_complex *H, const hs_complex *S, int N, hs_complex
     if (mode != HS_FP64 && mode != HS_FP64_3M) return -10;
     int rc = hs::check_device();
     if (rc != HS_OK) return rc;
-    if (workspace_bytes < hs::gep_workspace_bytes(N)) return HS_ERR_WORKSPACE;
+    if (workspace_bytes < hs::gep_workspace_bytes(N)) {
+        hs::set_error(HS_ERR_WORKSPACE, "workspace too small: the reduction needs " +
+                      std::to_string(hs::gep_workspace_bytes(N)) + " bytes, " +
+                      std::to_string(workspace_bytes) + " given");
+        return HS_ERR_WORKSPACE;
+    }
     hipError_t e = hs::launch_gep(c2(H), c2(S), N, c2(L), c2(Ht), info,
                                   static_cast<char *>(workspace), static_cast<hipStream_t>(stream),
                                   mode == HS_FP64_3M);
@@ -423,13 +445,13 @@ int hs_gep_check_schedule(int N, int mode, int drop_wait, char *report, size_t r
 }
 
 const char *hs_status_string(int status) {
-    const std::string &m = hs::last_error();
+    const char *m = hs::message_for(status);
     switch (status) {
         case HS_OK: return "success";
-        case HS_ERR_HIP: return m.empty() ? "HIP runtime error" : m.c_str();
-        case HS_ERR_WORKSPACE: return "workspace too small";
-        case HS_ERR_NOMEM: return m.empty() ? "out of device memory" : m.c_str();
-        case HS_ERR_UNSUPPORTED: return m.empty() ? "unsupported size or device" : m.c_str();
+        case HS_ERR_HIP: return m ? m : "HIP runtime error";
+        case HS_ERR_WORKSPACE: return m ? m : "workspace too small";
+        case HS_ERR_NOMEM: return m ? m : "out of device memory";
+        case HS_ERR_UNSUPPORTED: return m ? m : "unsupported size or device";
         default:
             if (status < 0) return "invalid argument (-status is its 1-based position)";
             return "unknown status";

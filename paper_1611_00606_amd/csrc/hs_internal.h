@@ -40,9 +40,20 @@ hipError_t launch_prep(const Atoms &at, const double2 *T_AA, const double2 *T_BB
 // Per-atom products (Alg. 1 first loop and second-loop branches):
 //   Z_a = T_AB,a^H A_a + M2_a^H B_a      (= T^BA_a A_a + 1/2 T^BB_a B_a)
 //   W_a = M1_a^H A_a                     (= Y_a or X_a)
+// sel: the preparation's [3K] row selectors (sel[2K + r] != 0 on the rows of
+// atoms on the failure branch); on the other atoms M1_a = C_a is lower
+// triangular and W_a's rows contract only over l >= their own index.
 hipError_t launch_atom(const Atoms &at, int n_g, const double2 *A, const double2 *B,
                        const double2 *T_AB, const double2 *M1, const double2 *M2,
-                       double2 *Z, double2 *W, hipStream_t st);
+                       const int *sel, double2 *Z, double2 *W, hipStream_t st);
+
+// Start of the contraction of a W_a tile whose output rows begin at m0: with
+// C_a lower triangular, conj(C_a[l][m]) is zero for l < m, so rows l < m0
+// add nothing to rows m >= m0 (the product is a triangular multiply); the
+// failure branch's Hermitian T^AA_a is full.
+__device__ __forceinline__ int w_contraction_start(bool failing, int m0) {
+    return failing ? 0 : m0;
+}
 
 // Large reductions (Alg. 1's zher2k, zherk pair of S, failure-branch zgemm
 // and HPD zherk) into the lower triangles of H and S (complex FP64 MFMA;
@@ -52,8 +63,8 @@ hipError_t launch_reduce(int K, int n_g, const double2 *A, const double2 *B,
                          const double *d, double2 *H, double2 *S, hipStream_t st, bool g3);
 
 // Error bookkeeping shared by the C entry points (thread-local message).
-void set_error(const std::string &msg);
-const std::string &last_error();
+void set_error(int status, const std::string &msg);
+const char *message_for(int status);   // the last message if it explains `status`, else NULL
 int hip_fail(hipError_t e, const char *where);   // records the message, returns HS_ERR_HIP
 int check_device();                              // HS_OK on gfx950, else an error status
 int num_cus();                                   // compute units of the current device
@@ -207,5 +218,19 @@ hipError_t enqueue_kpoint(const AtomPlan &p, const AtomBufs &ab, int n_g, int mo
                           const double2 *A, const double2 *B, const double2 *T_AB,
                           const KpointBufs &kb, double2 *H, double2 *S, hipStream_t st,
                           const hipEvent_t *ev, const AtomStage &stage = AtomStage());
+
+// Argument checks shared by the one-shot entry points (hs_build's argument
+// order; per_atom: N_L comes from a per-atom table and is not checked here).
+int check_build_args(const hs_complex *A, const hs_complex *B, const hs_complex *T_AA,
+                     const hs_complex *T_AB, const hs_complex *T_BB, const hs_complex *U,
+                     int N_A, int N_L, int N_G, const hs_complex *H, const hs_complex *S,
+                     bool per_atom);
+// One-shot build on stream st with the workspace ws (atom part, then
+// k-point part; p.atom_bytes() + p.kpoint_bytes(n_g, mode) bytes). Returns
+// HS_OK or a status; enqueues only.
+int run_build(const AtomPlan &p, int n_g, int mode, const hs_complex *A, const hs_complex *B,
+              const hs_complex *T_AA, const hs_complex *T_AB, const hs_complex *T_BB,
+              const hs_complex *U, hs_complex *H, hs_complex *S, char *ws, int32_t *info_user,
+              hipStream_t st, void **events, bool batch, const hs_tuning *tuning);
 
 }  // namespace hs

@@ -70,7 +70,7 @@ int hs_ctx_create(const hs_complex *T_AA, const hs_complex *T_AB, const hs_compl
     const size_t tbytes = 16 * (size_t)c->plan.t_total;
     e = hipMalloc(&c->mem, abytes + tbytes);
     if (e == hipErrorOutOfMemory) {
-        hs::set_error("context allocation");
+        hs::set_error(HS_ERR_NOMEM, "context allocation");
         return HS_ERR_NOMEM;
     }
     if (e != hipSuccess) return hs::hip_fail(e, "hipMalloc");
@@ -122,8 +122,12 @@ int hs_ctx_build(const hs_ctx *ctx, const hs_complex *A, const hs_complex *B, in
     if (!opt || !hs::valid_mode(opt->mode) || (opt->batch != 0 && opt->batch != 1)) return -7;
     if (opt->batch && !hs::BatchPlan::valid(ctx->plan, opt->tuning ? opt->tuning->cfg : nullptr))
         return -7;
-    if (!opt->workspace || opt->workspace_bytes < ctx->plan.kpoint_bytes(N_G, opt->mode))
+    if (!opt->workspace || opt->workspace_bytes < ctx->plan.kpoint_bytes(N_G, opt->mode)) {
+        hs::set_error(HS_ERR_WORKSPACE, "workspace too small: the k-point needs " +
+                      std::to_string(ctx->plan.kpoint_bytes(N_G, opt->mode)) + " bytes, " +
+                      std::to_string(opt->workspace ? opt->workspace_bytes : 0) + " given");
         return HS_ERR_WORKSPACE;
+    }
     hipStream_t st = static_cast<hipStream_t>(opt->stream);
     hipEvent_t ev[HS_NUM_PHASE_EVENTS] = {};
     if (opt->phase_events)
@@ -288,7 +292,7 @@ int hs_server_create(hs_ctx *ctx, int n_slots, size_t arena_bytes, int mode, hs_
     s->arena_bytes = arena_bytes;
     hipError_t e = hipMalloc(&s->arena_mem, arena_bytes);
     if (e == hipErrorOutOfMemory) {
-        hs::set_error("server arena allocation");
+        hs::set_error(HS_ERR_NOMEM, "server arena allocation");
         return HS_ERR_NOMEM;
     }
     if (e != hipSuccess) return hs::hip_fail(e, "hipMalloc");
@@ -312,7 +316,7 @@ int hs_server_submit(hs_server *s, const hs_request *req) {
     if (!s) return -1;
     if (!req || req->N_G < 1 || !req->A_host || !req->B_host || req->ld < req->N_G) return -2;
     if (footprint(s->ctx->plan, req->N_G, s->mode) > s->arena_bytes) {
-        hs::set_error("request footprint exceeds the server arena");
+        hs::set_error(HS_ERR_NOMEM, "request footprint exceeds the server arena");
         return HS_ERR_NOMEM;
     }
     Live *l = new Live;

@@ -61,7 +61,7 @@ int tune_one(int nl, int n_g, int reps, hipStream_t st, float *ms_out) {
     char *mem = nullptr;
     hipError_t e = hipMalloc(&mem, total);
     if (e == hipErrorOutOfMemory) {
-        hs::set_error("autotune allocation");
+        hs::set_error(HS_ERR_NOMEM, "autotune allocation");
         return HS_ERR_NOMEM;
     }
     if (e != hipSuccess) return hs::hip_fail(e, "hipMalloc");

@@ -1,6 +1,8 @@
 // Per-atom products of Alg. 1, as complex MFMA tiles:
 //   first loop     Z_a = T^BA_a A_a + 1/2 T^BB_a B_a = T_AB,a^H A_a + M2_a^H B_a
-//   second loop    W_a = M1_a^H A_a  = C_a^H A_a (success, Y_a)
+//   second loop    W_a = M1_a^H A_a  = C_a^H A_a (success, Y_a; C_a lower
+//                                    triangular, so a row tile's contraction
+//                                    starts at its first row)
 //                                    or T^AA_a A_a (failure, X_a)
 // with M1, M2 prepared by k_prep (M2 = 1/2 T^BB_a and, on failure,
 // M1 = T^AA_a, both Hermitian, so M^H = M).
@@ -21,7 +23,7 @@ __global__ void __launch_bounds__(C::NT)
 k_atom(Atoms at, int n_g, int mtiles, const double2 *__restrict__ A,
        const double2 *__restrict__ B, const double2 *__restrict__ T_AB,
        const double2 *__restrict__ M1, const double2 *__restrict__ M2,
-       double2 *__restrict__ Z, double2 *__restrict__ W) {
+       const int *__restrict__ sel, double2 *__restrict__ Z, double2 *__restrict__ W) {
     __shared__ double2 lds[C::LDS_ELEMS];
 
     const int a = blockIdx.y / mtiles;
@@ -50,11 +52,13 @@ k_atom(Atoms at, int n_g, int mtiles, const double2 *__restrict__ A,
         tab.P[1] = M2 + t0;
         tab.Q[1] = Ba;
     } else {
+        const int k0 = w_contraction_start(sel[2 * at.K + r0] != 0, m0);
         tab.nseg = 1;
-        tab.P[0] = M1 + t0;
-        tab.Q[0] = Aa;
-        tab.P[1] = M1 + t0;
-        tab.Q[1] = Aa;
+        tab.len = n - k0;
+        tab.P[0] = M1 + t0 + (long long)k0 * n;
+        tab.Q[0] = Aa + (long long)k0 * n_g;
+        tab.P[1] = tab.P[0];
+        tab.Q[1] = tab.Q[0];
     }
 
     Acc<C> acc;
@@ -81,11 +85,11 @@ using AtomCfg128 = TileCfg<128, 64, 16, 2, 2>;
 template <class C>
 hipError_t launch_atom_cfg(const Atoms &at, int n_g, const double2 *A, const double2 *B,
                            const double2 *T_AB, const double2 *M1, const double2 *M2,
-                           double2 *Z, double2 *W, hipStream_t st) {
+                           const int *sel, double2 *Z, double2 *W, hipStream_t st) {
     const int mtiles = (at.max_nl + C::BM - 1) / C::BM;
     dim3 grid((n_g + C::BN - 1) / C::BN, at.n_atoms * mtiles, 2);
     hipLaunchKernelGGL(k_atom<C>, grid, dim3(C::NT), 0, st, at, n_g, mtiles, A, B, T_AB, M1,
-                       M2, Z, W);
+                       M2, sel, Z, W);
     return hipGetLastError();
 }
 
@@ -93,10 +97,10 @@ hipError_t launch_atom_cfg(const Atoms &at, int n_g, const double2 *A, const dou
 
 hipError_t launch_atom(const Atoms &at, int n_g, const double2 *A, const double2 *B,
                        const double2 *T_AB, const double2 *M1, const double2 *M2,
-                       double2 *Z, double2 *W, hipStream_t st) {
+                       const int *sel, double2 *Z, double2 *W, hipStream_t st) {
     if (at.max_nl <= 64)
-        return launch_atom_cfg<AtomCfg64>(at, n_g, A, B, T_AB, M1, M2, Z, W, st);
-    return launch_atom_cfg<AtomCfg128>(at, n_g, A, B, T_AB, M1, M2, Z, W, st);
+        return launch_atom_cfg<AtomCfg64>(at, n_g, A, B, T_AB, M1, M2, sel, Z, W, st);
+    return launch_atom_cfg<AtomCfg128>(at, n_g, A, B, T_AB, M1, M2, sel, Z, W, st);
 }
 
 }  // namespace hs

@@ -67,7 +67,8 @@ struct BatchArgs {
 };
 
 template <class C>
-__device__ __forceinline__ void product_tile(int which, int r0, int n, long long t0, int loc,
+__device__ __forceinline__ void product_tile(int which, bool failing, int r0, int n, long long t0,
+                                             int loc,
                                              int n_g, const double2 *A, const double2 *B,
                                              const double2 *T_AB, const double2 *M1,
                                              const double2 *M2, double2 *Z, double2 *W,
@@ -91,11 +92,13 @@ __device__ __forceinline__ void product_tile(int which, int r0, int n, long long
         tab.P[1] = M2 + t0;
         tab.Q[1] = Ba;
     } else {
+        const int k0 = w_contraction_start(failing, m0);
         tab.nseg = 1;
-        tab.P[0] = M1 + t0;
-        tab.Q[0] = Aa;
-        tab.P[1] = M1 + t0;
-        tab.Q[1] = Aa;
+        tab.len = n - k0;
+        tab.P[0] = M1 + t0 + (long long)k0 * n;
+        tab.Q[0] = Aa + (long long)k0 * n_g;
+        tab.P[1] = tab.P[0];
+        tab.Q[1] = tab.Q[0];
     }
     Acc<C> acc;
     ztile_run<C>(tab, m0, n, n0, n_g, acc, lds);
@@ -183,30 +186,32 @@ k_batch(BatchArgs args) {
         const int n = at.row_off[atom + 1] - r0;
         const long long t0 = at.t_off[atom];
         const int which = kind - 1;
+        // W tiles of an atom with a Cholesky factor contract a triangle only
+        const bool failing = which == 1 && args.sel[2 * at.K + r0] != 0;
         double2 *tl = reinterpret_cast<double2 *>(lds);
         switch (args.cfg[n]) {
             case 0:
-                product_tile<Cfg0>(which, r0, n, t0, loc, args.n_g, args.A, args.B, args.T_AB,
+                product_tile<Cfg0>(which, failing, r0, n, t0, loc, args.n_g, args.A, args.B, args.T_AB,
                                    args.M1, args.M2, args.Z, args.W, tl);
                 break;
             case 1:
-                product_tile<Cfg1>(which, r0, n, t0, loc, args.n_g, args.A, args.B, args.T_AB,
+                product_tile<Cfg1>(which, failing, r0, n, t0, loc, args.n_g, args.A, args.B, args.T_AB,
                                    args.M1, args.M2, args.Z, args.W, tl);
                 break;
             case 2:
-                product_tile<Cfg2>(which, r0, n, t0, loc, args.n_g, args.A, args.B, args.T_AB,
+                product_tile<Cfg2>(which, failing, r0, n, t0, loc, args.n_g, args.A, args.B, args.T_AB,
                                    args.M1, args.M2, args.Z, args.W, tl);
                 break;
             case 3:
-                product_tile<Cfg3>(which, r0, n, t0, loc, args.n_g, args.A, args.B, args.T_AB,
+                product_tile<Cfg3>(which, failing, r0, n, t0, loc, args.n_g, args.A, args.B, args.T_AB,
                                    args.M1, args.M2, args.Z, args.W, tl);
                 break;
             case 4:
-                product_tile<Cfg4>(which, r0, n, t0, loc, args.n_g, args.A, args.B, args.T_AB,
+                product_tile<Cfg4>(which, failing, r0, n, t0, loc, args.n_g, args.A, args.B, args.T_AB,
                                    args.M1, args.M2, args.Z, args.W, tl);
                 break;
             default:
-                product_tile<Cfg5>(which, r0, n, t0, loc, args.n_g, args.A, args.B, args.T_AB,
+                product_tile<Cfg5>(which, failing, r0, n, t0, loc, args.n_g, args.A, args.B, args.T_AB,
                                    args.M1, args.M2, args.Z, args.W, tl);
                 break;
         }

@@ -12,21 +12,25 @@
 //     S22 -= L21 L21^H                  lower triangle, contraction over 128
 //   invert, recursive over the same blocks (split at m):
 //     M21 = -M22 (L21 M11)              M = L^{-1}
-//   then, with MH = M^H = L^{-H} (upper triangular),
+//   then, with MH = M^H = L^{-H} (upper triangular), below N = 4096
 //     V  = H MH                         (= (L^{-1} H)^H for Hermitian H)
 //     Ht = V^H MH                       lower triangle, then mirrored
+//   and from N = 4096 on, with HL the lower triangle of H (half diagonal),
+//     WH = HL^H MH                      (= (M HL)^H, upper triangular)
+//     Ht = WH^H MH + M WH               two-term lower triangle, mirrored
 //
-// Work: N^3/3 complex multiply-adds for the factor and its inverse, N^3/2
-// for V, N^3/6 for the lower triangle of Ht (triangular operands skip their
-// zero blocks), N^3 in all = 8 N^3 real flops, against 7/6 N^3 (9.33 N^3) for
-// the Cholesky and two full triangular solves of the plain definition. The
-// explicit inverse of L is the usual choice for this reduction in FLAPW
-// eigensolvers; its error grows with cond(L) = cond(S)^{1/2} like that of
-// the substitutions.
+// Work: N^3/3 complex multiply-adds for the factor and its inverse; then
+// N^3/2 for V and N^3/6 for the lower triangle of Ht (triangular operands
+// skip their zero blocks), N^3 in all = 8 N^3 real flops; or, in the
+// two-term form, N^3/6 for WH and N^3/3 for Ht, 5N^3/6 in all = 20/3 N^3
+// real flops. The minimal count of the reduction (LAPACK's zpotrf + zhegst)
+// is 16/3 N^3. The explicit inverse of L is the usual choice for this
+// reduction in FLAPW eigensolvers; its error grows with cond(L) =
+// cond(S)^{1/2} like that of the substitutions.
 //
 // Once the factorization passes the top split of the inverse's recursion,
-// the leading block's inverse and the matching columns of V run on a third
-// stream beside it.
+// the leading block's inverse and the matching columns of the result run on
+// a third stream beside it.
 //
 // Storage (all N x N row-major complex): L (output; working copy of S's
 // lower triangle during the factorization), LH (panels L21^H, then V),

@@ -24,13 +24,6 @@
 // completes both outputs: upper = conj(lower), Im(diag) = 0.
 #include "hs_internal.h"
 #include "zmfma_direct.h"
-#include "zmfma_tile.h"
-
-// 1: operands move global -> LDS with direct loads (zmfma_direct.h);
-// 0: through registers (ztile_run)
-#ifndef HS_RED_DIRECT
-#define HS_RED_DIRECT 1
-#endif
 
 namespace hs {
 
@@ -140,12 +133,7 @@ k_reduce(RedArgs args) {
         t.palt = args.A;
         t.sel = args.sel;      // [3K]: 0 on the first two segments
         t.qscale = nullptr;
-#if HS_RED_DIRECT
         ztile_direct<C, 3, true, false, G3>(t, m0, args.n_g, n0, args.n_g, acc, lds);
-#else
-        static_assert(!G3, "the 3M form needs the direct loader");
-        ztile_run<C>(t, m0, args.n_g, n0, args.n_g, acc, lds);
-#endif
     } else {
         // A^H A + B^H diag(|u|^2) B
         Segs<2, false, true> t;
@@ -159,11 +147,7 @@ k_reduce(RedArgs args) {
         t.palt = nullptr;
         t.sel = nullptr;
         t.qscale = args.d;     // [2K]: 1 on A's rows, |u|^2 on B's rows
-#if HS_RED_DIRECT
         ztile_direct<C, 2, false, true, G3>(t, m0, args.n_g, n0, args.n_g, acc, lds);
-#else
-        ztile_run<C>(t, m0, args.n_g, n0, args.n_g, acc, lds);
-#endif
     }
 
     double2 *out = isH ? args.H : args.S;

@@ -27,15 +27,6 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-// 1: software-pipelined LDS fragment reads interleaved with the MFMAs.
-#ifndef HS_TILE_PIPELINE
-#define HS_TILE_PIPELINE 1
-#endif
-// 1: the global prefetch stays at the top of each stage, the LDS store at its end.
-#ifndef HS_TILE_FENCE
-#define HS_TILE_FENCE 0
-#endif
-
 namespace hs {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -280,7 +271,6 @@ __device__ __forceinline__ void ztile_run(const Segs<NSEG, SEL, SCALE> &t, int m
             for (int j = 0; j < C::TN; ++j)
                 acc.im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, nbr[j], acc.im[i][j], 0, 0, 0);
     };
-#if HS_TILE_PIPELINE
     // Interleave the next step's TM+TN fragment reads with this step's
     // 4 TM TN MFMAs (one LDS read, then a few MFMAs), instead of letting the
     // scheduler hoist every read of the stage ahead of the MFMAs.
@@ -295,37 +285,30 @@ __device__ __forceinline__ void ztile_run(const Segs<NSEG, SEL, SCALE> &t, int m
         }
         __builtin_amdgcn_sched_group_barrier(0x008, NM - NR * PER, 0);
     };
-#endif
     static_assert((C::BK / 4) % 2 == 0, "K steps per stage must be even");
 
     for (int s = 0; s < nst; ++s) {
         fetch(s + 1);
         meta(s + 2);
-#if HS_TILE_FENCE
-        // keep the prefetch at the top of the stage: its loads then have the
-        // whole stage's MFMAs to land before the LDS store needs them
-        __builtin_amdgcn_sched_barrier(0);
-#endif
         const double2 *lp = lds + (s & 1) * C::BK * (C::BM + C::BN);
         const double2 *lq = lp + C::BK * C::BM;
         double2 fa0[C::TM], fb0[C::TN], fa1[C::TM], fb1[C::TN];
+        // The last stage can hold fewer than BK valid rows (the rest are
+        // zero-filled): when its second half holds none, its two K steps
+        // are skipped (they would add exact zeros). Short contractions - the
+        // per-atom products - save part of a stage this way.
+        const bool full = ktot - s * C::BK > C::BK / 2;
         ldfrag(lp, lq, 0, fa0, fb0);
 #pragma unroll
         for (int k4 = 0; k4 < C::BK / 4; k4 += 2) {
+            if (k4 >= C::BK / 8 && !full) break;
             ldfrag(lp, lq, k4 + 1, fa1, fb1);
             mma(fa0, fb0);
-#if HS_TILE_PIPELINE
             interleave();
-#endif
             if (k4 + 2 < C::BK / 4) ldfrag(lp, lq, k4 + 2, fa0, fb0);
             mma(fa1, fb1);
-#if HS_TILE_PIPELINE
             if (k4 + 2 < C::BK / 4) interleave();
-#endif
         }
-#if HS_TILE_FENCE
-        __builtin_amdgcn_sched_barrier(0);
-#endif
         stash((s + 1) & 1);
         __syncthreads();
     }
