@@ -207,6 +207,34 @@ int hs_build_ex(const hs_complex *A, const hs_complex *B,
                 hs_complex *H, hs_complex *S,
                 const hs_options *opt);
 
+/* Bytes of the device array that hs_build_static uses as its workspace. */
+#define HS_STATIC_SCRATCH_BYTES ((size_t)256 << 20)
+
+/*
+ * hs_build_static - hs_build_ex for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the build's workspace is a device array inside the
+ * library (HS_STATIC_SCRATCH_BYTES per device, held from the first call on
+ * that device until the process ends) instead of a caller buffer.
+ * Arguments 1..12 as hs_build_ex, except that opt->workspace must be NULL and
+ * opt->workspace_bytes 0 (else -12). Enqueues on opt->stream and returns
+ * (asynchronous); results are bitwise those of hs_build_ex with the same
+ * options. No device memory is allocated or freed: the first call on a
+ * device only looks up the array's address there. Returns what hs_build_ex
+ * returns, and 2 when hs_workspace_bytes(...) for these sizes and this mode
+ * exceeds HS_STATIC_SCRATCH_BYTES (hs_status_string(2) then names both
+ * sizes). Every call on one device uses the same array and the kernels
+ * clear what they need cleared; calls whose work overlaps on one device
+ * (different streams, or different host threads) race on it and give
+ * undefined results, so callers serialize them (one stream is enough).
+ */
+int hs_build_static(const hs_complex *A, const hs_complex *B,
+                    const hs_complex *T_AA, const hs_complex *T_AB,
+                    const hs_complex *T_BB, const hs_complex *U,
+                    int N_A, int N_L, int N_G,
+                    hs_complex *H, hs_complex *S,
+                    const hs_options *opt);
+
 /* Human-readable text for a status code (thread-local last HIP message for 1). */
 const char *hs_status_string(int status);
 

@@ -19,12 +19,14 @@ from ._binding import (  # noqa: F401
     HS_MAX_NL,
     HS_NUM_PHASE_EVENTS,
     HS_NUM_TILE_CONFIGS,
+    HS_STATIC_SCRATCH_BYTES,
     HSError,
     hs_tuning,
     LIB_PATH,
     load_library,
     hs_build,
     hs_build_ex,
+    hs_build_static,
     hs_workspace_bytes,
     hs_status_string,
 )

@@ -30,6 +30,7 @@ HS_FP64_3M = 3
 HS_MAX_NL = 128
 HS_NUM_PHASE_EVENTS = 5
 HS_NUM_TILE_CONFIGS = 6
+HS_STATIC_SCRATCH_BYTES = 256 << 20
 
 
 class HSError(RuntimeError):
@@ -101,6 +102,8 @@ def load_library() -> ctypes.CDLL:
     lib.hs_build.restype = i32
     lib.hs_build_ex.argtypes = [vp] * 6 + [i32, i32, i32, vp, vp, ctypes.POINTER(hs_options)]
     lib.hs_build_ex.restype = i32
+    lib.hs_build_static.argtypes = [vp] * 6 + [i32, i32, i32, vp, vp, ctypes.POINTER(hs_options)]
+    lib.hs_build_static.restype = i32
     lib.hs_workspace_bytes.argtypes = [i32, ctypes.POINTER(ctypes.c_int32), i32, i32, i32]
     lib.hs_workspace_bytes.restype = ctypes.c_size_t
     lib.hs_status_string.argtypes = [i32]
@@ -215,20 +218,9 @@ def _tuning_ptr(tuning):
     return ctypes.pointer(tuning)
 
 
-def hs_build_ex(A, B, T_AA, T_AB, T_BB, U, N_A, N_L, N_G, H, S, *, workspace,
-                info=None, stream=None, mode: int = HS_FP64, nl_per_atom=None,
-                phase_events=None, batch: int = 0, tuning=None, check: bool = True) -> int:
-    """Asynchronous build on `stream` (default: torch's current stream).
-
-    workspace: uint8 device tensor of >= hs_workspace_bytes(...) bytes.
-    info: int32 device tensor [N_A] or None.
-    nl_per_atom: host sequence of N_A ints, or None for a uniform N_L.
-    phase_events: None or a sequence of HS_NUM_PHASE_EVENTS raw hipEvent_t handles.
-    batch: 1 runs the per-atom stage as the batched persistent launch.
-    tuning: None or an hs_tuning (tile shape per N_L) for the batched launch.
-    """
+def _options(workspace, info, stream, mode, nl_per_atom, phase_events, batch, tuning):
+    """hs_options for the one-shot builds; returns (opt, objects to keep alive)."""
     import torch
-    _check_c128(A, B, T_AA, T_AB, T_BB, U, H, S)
     if stream is None:
         stream = torch.cuda.current_stream().cuda_stream
     elif not isinstance(stream, int):
@@ -253,10 +245,42 @@ def hs_build_ex(A, B, T_AA, T_AB, T_BB, U, N_A, N_L, N_G, H, S, *, workspace,
             raise ValueError("phase_events needs HS_NUM_PHASE_EVENTS handles")
         ev = (ctypes.c_void_p * HS_NUM_PHASE_EVENTS)(*phase_events)
         opt.phase_events = ctypes.cast(ev, ctypes.POINTER(ctypes.c_void_p))
+    return opt, (arr, tp, ev)
+
+
+def hs_build_ex(A, B, T_AA, T_AB, T_BB, U, N_A, N_L, N_G, H, S, *, workspace,
+                info=None, stream=None, mode: int = HS_FP64, nl_per_atom=None,
+                phase_events=None, batch: int = 0, tuning=None, check: bool = True) -> int:
+    """Asynchronous build on `stream` (default: torch's current stream).
+
+    workspace: uint8 device tensor of >= hs_workspace_bytes(...) bytes.
+    info: int32 device tensor [N_A] or None.
+    nl_per_atom: host sequence of N_A ints, or None for a uniform N_L.
+    phase_events: None or a sequence of HS_NUM_PHASE_EVENTS raw hipEvent_t handles.
+    batch: 1 runs the per-atom stage as the batched persistent launch.
+    tuning: None or an hs_tuning (tile shape per N_L) for the batched launch.
+    """
+    _check_c128(A, B, T_AA, T_AB, T_BB, U, H, S)
+    opt, keep = _options(workspace, info, stream, mode, nl_per_atom, phase_events, batch, tuning)
     rc = load_library().hs_build_ex(_ptr(A), _ptr(B), _ptr(T_AA), _ptr(T_AB), _ptr(T_BB), _ptr(U),
                                     int(N_A), int(N_L), int(N_G), _ptr(H), _ptr(S),
                                     ctypes.byref(opt))
-    del arr
+    del keep
+    return _raise(rc, check)
+
+
+def hs_build_static(A, B, T_AA, T_AB, T_BB, U, N_A, N_L, N_G, H, S, *, info=None,
+                    stream=None, mode: int = HS_FP64, nl_per_atom=None, phase_events=None,
+                    batch: int = 0, tuning=None, check: bool = True) -> int:
+    """hs_build_ex without a workspace: the library's fixed device array of
+    HS_STATIC_SCRATCH_BYTES serves as one (no device allocation). Calls
+    that overlap on one device race on that array."""
+    _check_c128(A, B, T_AA, T_AB, T_BB, U, H, S)
+    opt, keep = _options(None, info, stream, mode, nl_per_atom, phase_events, batch, tuning)
+    rc = load_library().hs_build_static(_ptr(A), _ptr(B), _ptr(T_AA), _ptr(T_AB), _ptr(T_BB),
+                                        _ptr(U), int(N_A), int(N_L), int(N_G), _ptr(H), _ptr(S),
+                                        ctypes.byref(opt))
+    del keep
     return _raise(rc, check)
 
 

@@ -226,3 +226,33 @@ def test_gep_argument_checks():
         assert lib.hs_gep_reduce_ex(*a, P.HS_FP64_3M) == -(pos + 1)
     for bad_mode in (P.HS_SPLIT_F16, P.HS_SPLIT_I8, 4, -1):
         assert lib.hs_gep_reduce_ex(*args, bad_mode) == -10
+
+
+def test_build_static_host_checks():
+    """hs_build_static: option checks, and builds larger than its device
+    array rejected on the host before any device call."""
+    lib = P.load_library()
+    assert lib.hs_build_static(*[FAKE] * 6, 2, 4, 8, FAKE, FAKE, None) == -12
+    opt = Bd.hs_options()
+    opt.workspace = FAKE
+    opt.workspace_bytes = 1 << 30
+    assert lib.hs_build_static(*[FAKE] * 6, 2, 4, 8, FAKE, FAKE, ctypes.byref(opt)) == -12
+    opt = Bd.hs_options()
+    assert lib.hs_build_static(None, *[FAKE] * 5, 2, 4, 8, FAKE, FAKE, ctypes.byref(opt)) == -1
+    assert lib.hs_build_static(*[FAKE] * 6, 2, 4, 0, FAKE, FAKE, ctypes.byref(opt)) == -9
+    opt.mode = 9
+    assert lib.hs_build_static(*[FAKE] * 6, 2, 4, 8, FAKE, FAKE, ctypes.byref(opt)) == -12
+    text = open(os.path.join(ROOT, "include", "hs_build.h")).read()
+    m = re.search(r"#define HS_STATIC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == P.HS_STATIC_SCRATCH_BYTES
+    for mode, (n_a, n_l, n_g) in ((0, (100, 81, 8000)), (1, (10, 100, 2500))):
+        need = P.hs_workspace_bytes(n_a, None, n_l, n_g, mode)
+        assert need > P.HS_STATIC_SCRATCH_BYTES
+        opt = Bd.hs_options()
+        opt.mode = mode
+        assert lib.hs_build_static(*[FAKE] * 6, n_a, n_l, n_g, FAKE, FAKE,
+                                   ctypes.byref(opt)) == P.HS_ERR_WORKSPACE
+        msg = P.hs_status_string(P.HS_ERR_WORKSPACE)
+        assert str(need) in msg and str(P.HS_STATIC_SCRATCH_BYTES) in msg
+    # the largest plain-FP64 builds it takes: the 32-atom N_L = 49 case at N_G = 2000
+    assert P.hs_workspace_bytes(32, None, 49, 2000, 0) <= P.HS_STATIC_SCRATCH_BYTES
