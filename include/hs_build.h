@@ -396,13 +396,15 @@ void hs_ctx_destroy(hs_ctx *ctx);
 /* ------------------------------------------------------------------------
  * Serving loop: continuous batching of k-point builds on one context.
  *
- * Requests (one k-point each, any N_G) are queued on submit and admitted in
- * arrival order as soon as a slot (a HIP stream) is free and their device
- * footprint (hs_ctx_footprint_bytes) fits in the free part of the server's
- * device arena. An admitted request copies its A, B from host memory, builds
- * on its slot's stream, and keeps H, S in the arena until released, so work
- * of several requests overlaps on the device. All calls are host-side and
- * non-blocking except hs_server_destroy; one thread drives a server.
+ * Requests (one k-point each, any N_G) are queued on submit and admitted as
+ * soon as a slot (a HIP stream) is free and their device footprint
+ * (hs_ctx_footprint_bytes) fits in the free part of the server's device
+ * arena: in arrival order by default, or letting later requests pass one
+ * that waits for arena space (hs_server_set_admission). An admitted request
+ * copies its A, B from host memory, builds on its slot's stream, and keeps
+ * H, S in the arena until released, so work of several requests overlaps on
+ * the device. All calls are host-side and non-blocking except
+ * hs_server_destroy; one thread drives a server.
  * ---------------------------------------------------------------------- */
 typedef struct hs_server hs_server;
 
@@ -425,6 +427,21 @@ typedef struct {
 /* Arguments: 1 ctx (must outlive the server), 2 n_slots >= 1,
  * 3 arena_bytes (device memory reserved once, here), 4 mode, 5 out. */
 int hs_server_create(hs_ctx *ctx, int n_slots, size_t arena_bytes, int mode, hs_server **out);
+
+/* Admission policies (hs_server_set_admission). */
+enum {
+    HS_ADMIT_FIFO = 0,    /* arrival order; a request that does not fit the free
+                             arena holds back every later one (the default) */
+    HS_ADMIT_BYPASS = 1   /* a later request that fits may start while an earlier
+                             one waits; a waiting request is passed at most
+                             max_bypass times, then nothing behind it starts
+                             until it has */
+};
+
+/* Arguments: 1 srv, 2 policy (HS_ADMIT_*), 3 max_bypass >= 0 (HS_ADMIT_BYPASS
+ * only). Applies from the next hs_server_progress on. Returns 0, -1 (srv
+ * NULL), -2 (unknown policy) or -3 (max_bypass < 0). */
+int hs_server_set_admission(hs_server *srv, int policy, int max_bypass);
 
 /* Queue a request (host memory must stay valid until its result is popped).
  * Returns HS_ERR_NOMEM (3) when its footprint exceeds the whole arena. */

@@ -20,6 +20,8 @@ from ._binding import (  # noqa: F401
     HS_NUM_PHASE_EVENTS,
     HS_NUM_TILE_CONFIGS,
     HS_STATIC_SCRATCH_BYTES,
+    HS_ADMIT_FIFO,
+    HS_ADMIT_BYPASS,
     HSError,
     hs_tuning,
     LIB_PATH,
@@ -40,6 +42,7 @@ from ._binding import (  # noqa: F401,E402
     hs_ctx_destroy,
     hs_server_create,
     hs_server_submit,
+    hs_server_set_admission,
     hs_server_progress,
     hs_server_pop,
     hs_server_release,

@@ -31,6 +31,8 @@ HS_MAX_NL = 128
 HS_NUM_PHASE_EVENTS = 5
 HS_NUM_TILE_CONFIGS = 6
 HS_STATIC_SCRATCH_BYTES = 256 << 20
+HS_ADMIT_FIFO = 0
+HS_ADMIT_BYPASS = 1
 
 
 class HSError(RuntimeError):
@@ -128,6 +130,8 @@ def load_library() -> ctypes.CDLL:
     lib.hs_server_create.restype = i32
     lib.hs_server_submit.argtypes = [vp, ctypes.POINTER(hs_request)]
     lib.hs_server_submit.restype = i32
+    lib.hs_server_set_admission.argtypes = [vp, i32, i32]
+    lib.hs_server_set_admission.restype = i32
     lib.hs_server_progress.argtypes = [vp]
     lib.hs_server_progress.restype = i32
     lib.hs_server_pop.argtypes = [vp, ctypes.POINTER(hs_result)]
@@ -362,6 +366,10 @@ def hs_server_create(ctx, n_slots, arena_bytes, mode=HS_FP64) -> int:
 def hs_server_submit(srv, rid, N_G, A_host_ptr, B_host_ptr, ld, check=True) -> int:
     req = hs_request(int(rid), int(N_G), A_host_ptr, B_host_ptr, int(ld))
     return _raise(load_library().hs_server_submit(srv, ctypes.byref(req)), check)
+
+
+def hs_server_set_admission(srv, policy: int, max_bypass: int = 0, check=True) -> int:
+    return _raise(load_library().hs_server_set_admission(srv, int(policy), int(max_bypass)), check)
 
 
 def hs_server_progress(srv) -> int:

@@ -7,24 +7,24 @@
 // costs the per-atom products and the two reductions only.
 //
 // The server owns one device arena and n_slots HIP streams (default
-// priority). Requests are admitted in arrival order when a slot is free and
-// their footprint fits in the arena (first fit over a free list); each
-// admitted request copies its A, B (2-D copies from the caller's host rows),
-// builds on its slot's stream, and a host callback on that stream stamps the
-// completion time. Results stay in the arena until released.
+// priority). Requests are admitted when a slot is free and their footprint
+// fits in the arena (first fit over a free list), in arrival order or, with
+// the bypass policy, letting later requests that fit pass a waiting one a
+// bounded number of times (serving_sched.h); each admitted request copies its
+// A, B (2-D copies from the caller's host rows), builds on its slot's stream,
+// and a host callback on that stream stamps the completion time. Results
+// stay in the arena until released.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
 #include <chrono>
 #include <cstring>
-#include <deque>
-#include <map>
 #include <memory>
-#include <unordered_map>
 #include <vector>
 
 #include "../../include/hs_build.h"
 #include "hs_internal.h"
+#include "serving_sched.h"
 
 struct hs_ctx {
     hs::AtomPlan plan;
@@ -36,8 +36,7 @@ struct hs_ctx {
 
 namespace {
 
-constexpr size_t ALIGN = 256;
-size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+using hs::serve::align_up;
 
 size_t footprint(const hs::AtomPlan &p, int n_g, int mode) {
     const size_t ab = align_up(16 * (size_t)p.K * (size_t)n_g);
@@ -156,73 +155,23 @@ void hs_ctx_destroy(hs_ctx *ctx) {
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
-// Server
+// Server: the device side of the serving loop. Admission, the arena's free
+// list and the completion bookkeeping are serving_sched.h's Scheduler; this
+// part copies an admitted request's inputs, enqueues its build on its slot's
+// stream and stamps its completion from a host callback on that stream.
 
 namespace {
 
 using Clock = std::chrono::steady_clock;
 
-// First-fit allocator over [0, size) with coalescing free list.
-class Arena {
-   public:
-    void init(size_t size) {
-        free_.clear();
-        free_[0] = size;
-        used_ = 0;
-    }
-    bool alloc(size_t n, size_t &off) {
-        n = align_up(n);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= n) {
-                off = it->first;
-                const size_t rest = it->second - n;
-                free_.erase(it);
-                if (rest) free_[off + n] = rest;
-                used_ += n;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off, size_t n) {
-        n = align_up(n);
-        used_ -= n;
-        auto it = free_.emplace(off, n).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-    size_t used() const { return used_; }
-
-   private:
-    std::map<size_t, size_t> free_;
-    size_t used_ = 0;
-};
-
-struct Live {
+struct Live : hs::serve::Request {
     hs_request req;
-    size_t off = 0, bytes = 0;
-    int slot = -1;
-    int status = 0;
-    double t_submit = 0, t_admit = 0;
-    std::atomic<double> t_done{0.0};
-    std::atomic<int> done{0};
     Clock::time_point epoch;
 };
 
 void on_done(void *p) {
     Live *l = static_cast<Live *>(p);
-    l->t_done.store(std::chrono::duration<double>(Clock::now() - l->epoch).count());
-    l->done.store(1, std::memory_order_release);
+    l->finish(std::chrono::duration<double>(Clock::now() - l->epoch).count());
 }
 
 }  // namespace
@@ -231,48 +180,58 @@ struct hs_server {
     hs_ctx *ctx = nullptr;
     int mode = HS_FP64;
     char *arena_mem = nullptr;
-    size_t arena_bytes = 0;
-    Arena arena;
+    std::unique_ptr<hs::serve::Scheduler> sched;
     std::vector<hipStream_t> streams;
-    std::vector<Live *> slot_req;              // request running on each slot
-    std::deque<Live *> queue;                  // submitted, not admitted
-    std::deque<Live *> done;                   // completed, not popped
-    std::unordered_map<int64_t, Live *> popped;  // popped, not released
     Clock::time_point epoch;
     double now() const { return std::chrono::duration<double>(Clock::now() - epoch).count(); }
 };
 
 namespace {
 
-// Launch one admitted request on its slot; returns a status.
-int launch(hs_server *s, Live *l) {
+// Device addresses of an admitted request's A, B, H, S and workspace.
+struct Placement {
+    hs_complex *A, *B, *H, *S;
+    char *ws;
+};
+Placement place(const hs_server *s, const Live *l) {
     const hs::AtomPlan &p = s->ctx->plan;
     const int n_g = l->req.N_G;
     char *base = s->arena_mem + l->off;
     const size_t ab = align_up(16 * (size_t)p.K * (size_t)n_g);
     const size_t hsz = align_up(16 * (size_t)n_g * (size_t)n_g);
-    hs_complex *A = reinterpret_cast<hs_complex *>(base);
-    hs_complex *B = reinterpret_cast<hs_complex *>(base + ab);
-    hs_complex *H = reinterpret_cast<hs_complex *>(base + 2 * ab);
-    hs_complex *S = reinterpret_cast<hs_complex *>(base + 2 * ab + hsz);
-    char *ws = base + 2 * ab + 2 * hsz;   // workspace sized for the server's mode
+    return {reinterpret_cast<hs_complex *>(base), reinterpret_cast<hs_complex *>(base + ab),
+            reinterpret_cast<hs_complex *>(base + 2 * ab),
+            reinterpret_cast<hs_complex *>(base + 2 * ab + hsz), base + 2 * ab + 2 * hsz};
+}
+
+// Launch one admitted request on its slot; returns a status. On failure the
+// slot's stream is drained first, so nothing of the request is still running.
+int launch(hs_server *s, Live *l) {
+    const hs::AtomPlan &p = s->ctx->plan;
+    const int n_g = l->req.N_G;
+    const Placement d = place(s, l);
     hipStream_t st = s->streams[l->slot];
     const size_t row = 16 * (size_t)n_g, pitch = 16 * (size_t)l->req.ld;
-    hipError_t e = hipMemcpy2DAsync(A, row, l->req.A_host, pitch, row, p.K, hipMemcpyHostToDevice, st);
+    int rc = HS_OK;
+    hipError_t e = hipMemcpy2DAsync(d.A, row, l->req.A_host, pitch, row, p.K, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
-        e = hipMemcpy2DAsync(B, row, l->req.B_host, pitch, row, p.K, hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return hs::hip_fail(e, "request input copy");
-    hs_options opt;
-    std::memset(&opt, 0, sizeof(opt));
-    opt.stream = st;
-    opt.workspace = ws;
-    opt.workspace_bytes = p.kpoint_bytes(n_g, s->mode);
-    opt.mode = s->mode;
-    int rc = hs_ctx_build(s->ctx, A, B, n_g, H, S, &opt);
-    if (rc != HS_OK) return rc;
-    e = hipLaunchHostFunc(st, on_done, l);
-    if (e != hipSuccess) return hs::hip_fail(e, "completion callback");
-    return HS_OK;
+        e = hipMemcpy2DAsync(d.B, row, l->req.B_host, pitch, row, p.K, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) rc = hs::hip_fail(e, "request input copy");
+    if (rc == HS_OK) {
+        hs_options opt;
+        std::memset(&opt, 0, sizeof(opt));
+        opt.stream = st;
+        opt.workspace = d.ws;
+        opt.workspace_bytes = p.kpoint_bytes(n_g, s->mode);
+        opt.mode = s->mode;
+        rc = hs_ctx_build(s->ctx, d.A, d.B, n_g, d.H, d.S, &opt);
+    }
+    if (rc == HS_OK) {
+        e = hipLaunchHostFunc(st, on_done, l);
+        if (e != hipSuccess) rc = hs::hip_fail(e, "completion callback");
+    }
+    if (rc != HS_OK) (void)hipStreamSynchronize(st);
+    return rc;
 }
 
 }  // namespace
@@ -289,16 +248,14 @@ int hs_server_create(hs_ctx *ctx, int n_slots, size_t arena_bytes, int mode, hs_
     std::unique_ptr<hs_server> s(new hs_server);
     s->ctx = ctx;
     s->mode = mode;
-    s->arena_bytes = arena_bytes;
     hipError_t e = hipMalloc(&s->arena_mem, arena_bytes);
     if (e == hipErrorOutOfMemory) {
         hs::set_error(HS_ERR_NOMEM, "server arena allocation");
         return HS_ERR_NOMEM;
     }
     if (e != hipSuccess) return hs::hip_fail(e, "hipMalloc");
-    s->arena.init(arena_bytes);
+    s->sched.reset(new hs::serve::Scheduler(n_slots, arena_bytes));
     s->streams.resize(n_slots, nullptr);
-    s->slot_req.assign(n_slots, nullptr);
     for (int i = 0; i < n_slots; ++i) {
         e = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking);
         if (e != hipSuccess) {
@@ -315,101 +272,64 @@ int hs_server_create(hs_ctx *ctx, int n_slots, size_t arena_bytes, int mode, hs_
 int hs_server_submit(hs_server *s, const hs_request *req) {
     if (!s) return -1;
     if (!req || req->N_G < 1 || !req->A_host || !req->B_host || req->ld < req->N_G) return -2;
-    if (footprint(s->ctx->plan, req->N_G, s->mode) > s->arena_bytes) {
+    const size_t bytes = footprint(s->ctx->plan, req->N_G, s->mode);
+    if (!s->sched->fits_ever(bytes)) {
         hs::set_error(HS_ERR_NOMEM, "request footprint exceeds the server arena");
         return HS_ERR_NOMEM;
     }
     Live *l = new Live;
     l->req = *req;
-    l->bytes = footprint(s->ctx->plan, req->N_G, s->mode);
+    l->id = req->id;
+    l->bytes = bytes;
     l->epoch = s->epoch;
-    l->t_submit = s->now();
-    s->queue.push_back(l);
+    s->sched->submit(l, s->now());
+    return HS_OK;
+}
+
+int hs_server_set_admission(hs_server *s, int policy, int max_bypass) {
+    if (!s) return -1;
+    if (policy != HS_ADMIT_FIFO && policy != HS_ADMIT_BYPASS) return -2;
+    if (max_bypass < 0) return -3;
+    s->sched->set_policy(policy, max_bypass);
     return HS_OK;
 }
 
 int hs_server_progress(hs_server *s) {
     if (!s) return -1;
-    // completions
-    for (size_t i = 0; i < s->slot_req.size(); ++i) {
-        Live *l = s->slot_req[i];
-        if (l && l->done.load(std::memory_order_acquire)) {
-            s->slot_req[i] = nullptr;
-            s->done.push_back(l);
-        }
-    }
-    // admissions, in arrival order
-    while (!s->queue.empty()) {
-        int slot = -1;
-        for (size_t i = 0; i < s->slot_req.size(); ++i)
-            if (!s->slot_req[i]) {
-                slot = (int)i;
-                break;
-            }
-        if (slot < 0) break;
-        Live *l = s->queue.front();
-        size_t off;
-        if (!s->arena.alloc(l->bytes, off)) break;
-        s->queue.pop_front();
-        l->off = off;
-        l->slot = slot;
-        l->t_admit = s->now();
-        s->slot_req[slot] = l;
-        const int rc = launch(s, l);
-        if (rc != HS_OK) {
-            // nothing more will complete on this request: drain what was
-            // enqueued for it (so its arena space is idle) and report it now
-            (void)hipStreamSynchronize(s->streams[slot]);
-            s->slot_req[slot] = nullptr;
-            l->status = rc;
-            l->t_done.store(s->now());
-            s->done.push_back(l);
-        }
-    }
-    return (int)s->done.size();
+    return s->sched->progress([s](hs::serve::Request *r) { return launch(s, static_cast<Live *>(r)); },
+                              s->now());
 }
 
 int hs_server_pop(hs_server *s, hs_result *out) {
     if (!s || !out) return -1;
-    if (s->done.empty()) return 0;
-    Live *l = s->done.front();
-    s->done.pop_front();
-    const hs::AtomPlan &p = s->ctx->plan;
-    const int n_g = l->req.N_G;
-    char *base = s->arena_mem + l->off;
-    const size_t ab = align_up(16 * (size_t)p.K * (size_t)n_g);
-    const size_t hsz = align_up(16 * (size_t)n_g * (size_t)n_g);
+    Live *l = static_cast<Live *>(s->sched->pop());
+    if (!l) return 0;
     out->id = l->req.id;
-    out->N_G = n_g;
+    out->N_G = l->req.N_G;
     out->status = l->status;
-    out->H = reinterpret_cast<hs_complex *>(base + 2 * ab);
-    out->S = reinterpret_cast<hs_complex *>(base + 2 * ab + hsz);
+    out->H = out->S = nullptr;
+    if (l->slot >= 0) {
+        const Placement d = place(s, l);
+        out->H = d.H;
+        out->S = d.S;
+    }
     out->t_submit = l->t_submit;
     out->t_admit = l->t_admit;
     out->t_done = l->t_done.load();
-    s->popped[l->req.id] = l;
     return 1;
 }
 
 int hs_server_release(hs_server *s, int64_t id) {
     if (!s) return -1;
-    auto it = s->popped.find(id);
-    if (it == s->popped.end()) return -2;
-    Live *l = it->second;
-    s->popped.erase(it);
-    if (l->slot >= 0) s->arena.release(l->off, l->bytes);
-    delete l;
+    hs::serve::Request *r = s->sched->release(id);
+    if (!r) return -2;
+    delete r;
     return HS_OK;
 }
 
-int hs_server_pending(const hs_server *s) {
-    if (!s) return 0;
-    int n = (int)s->queue.size() + (int)s->done.size();
-    for (Live *l : s->slot_req) n += l != nullptr;
-    return n;
-}
+int hs_server_pending(const hs_server *s) { return s ? s->sched->pending() : 0; }
 
-size_t hs_server_used_bytes(const hs_server *s) { return s ? s->arena.used() : 0; }
+size_t hs_server_used_bytes(const hs_server *s) { return s ? s->sched->used() : 0; }
 
 double hs_server_now(const hs_server *s) { return s ? s->now() : 0.0; }
 
@@ -419,10 +339,7 @@ void hs_server_destroy(hs_server *s) {
         (void)hipStreamSynchronize(st);
         (void)hipStreamDestroy(st);
     }
-    for (Live *l : s->slot_req) delete l;
-    for (Live *l : s->queue) delete l;
-    for (Live *l : s->done) delete l;
-    for (auto &kv : s->popped) delete kv.second;
+    s->sched->for_each([](hs::serve::Request *r) { delete r; });
     if (s->arena_mem) (void)hipFree(s->arena_mem);
     delete s;
 }

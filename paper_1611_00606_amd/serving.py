@@ -71,6 +71,9 @@ def _hip():
     rt = ctypes.CDLL("libamdhip64.so.7")
     rt.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
     rt.hipMemcpy.restype = ctypes.c_int
+    sz = ctypes.c_size_t
+    rt.hipMemcpy2D.argtypes = [ctypes.c_void_p, sz, ctypes.c_void_p, sz, sz, sz, ctypes.c_int]
+    rt.hipMemcpy2D.restype = ctypes.c_int
     return rt
 
 
@@ -81,6 +84,18 @@ def device_matrix_to_host(ptr: int, n: int) -> np.ndarray:
     if rc != 0:
         raise RuntimeError(f"hipMemcpy failed ({rc})")
     return out
+
+
+def device_columns_to_host(ptr: int, n: int, cols: Sequence[int]) -> np.ndarray:
+    """Columns `cols` of an [n][n] complex128 device matrix, as an [n][len(cols)]
+    host array (one strided copy per column)."""
+    out = np.empty((len(cols), n), np.complex128)
+    rt = _hip()
+    for j, g in enumerate(cols):
+        rc = rt.hipMemcpy2D(out[j].ctypes.data, 16, ptr + 16 * int(g), 16 * n, 16, n, 2)
+        if rc != 0:
+            raise RuntimeError(f"hipMemcpy2D failed ({rc})")
+    return out.T.copy()
 
 
 def percentile(x: Sequence[float], q: float) -> float:
@@ -95,10 +110,12 @@ def percentile(x: Sequence[float], q: float) -> float:
 class ServingLoop:
     """One hs_server over a Context: n_slots streams and a device arena."""
 
-    def __init__(self, ctx: Context, n_slots: int, arena_bytes: int, mode: int = B.HS_FP64):
+    def __init__(self, ctx: Context, n_slots: int, arena_bytes: int, mode: int = B.HS_FP64,
+                 admission: int = B.HS_ADMIT_FIFO, max_bypass: int = 0):
         self.ctx = ctx
         self.mode = int(mode)
         self.handle = B.hs_server_create(ctx.handle, n_slots, arena_bytes, mode)
+        B.hs_server_set_admission(self.handle, admission, max_bypass)
         self.arena_bytes = int(arena_bytes)
         self.n_slots = int(n_slots)
 
