@@ -135,11 +135,15 @@ typedef struct {
        caller; contents on entry are ignored. */
     void *workspace;
     size_t workspace_bytes;
-    /* device int32 [N_A] or NULL. On completion info[a] = 0 when T_AA_a had a
+    /* device int32 [N_A], or NULL when batch = 0 (required with batch = 1:
+       NULL returns -12). On completion info[a] = 0 when T_AA_a had a
        Cholesky factor (atom a took Alg. 1's success branch), else the 1-based
        index j of the first pivot d_j = T_jj - sum_{k<j} |C_jk|^2 that is not
        > 0 or is NaN (LAPACK zpotrf semantics; atom a took the failure
-       branch). */
+       branch). With batch = 1, info[a] = -1 for EVERY atom means that a
+       product tile of the batched launch gave up waiting for its atom's
+       preparation (a bounded wait that should never run out): H and S are
+       then undefined and the build must be repeated. */
     int32_t *info;
     /* hs_mode */
     int mode;

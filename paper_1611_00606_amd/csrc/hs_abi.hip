@@ -356,6 +356,9 @@ int hs_build_ex(const hs_complex *A, const hs_complex *B, const hs_complex *T_AA
     if (rc != 0) return rc;
     if (opt->batch && !hs::BatchPlan::valid(p, opt->tuning ? opt->tuning->cfg : nullptr))
         return -12;
+    // the batched launch reports a bounded wait that ran out through info
+    // (every entry -1), so it needs a caller-visible info array
+    if (opt->batch && !opt->info) return -12;
     if (reinterpret_cast<uintptr_t>(opt->workspace) % 16) return -12;   // 16-byte loads
     rc = hs::check_device();
     if (rc != HS_OK) return rc;

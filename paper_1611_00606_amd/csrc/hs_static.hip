@@ -64,6 +64,9 @@ extern "C" int hs_build_static(const hs_complex *A, const hs_complex *B, const h
     if (rc != 0) return rc;
     if (opt->batch && !hs::BatchPlan::valid(p, opt->tuning ? opt->tuning->cfg : nullptr))
         return -12;
+    // the batched launch reports a bounded wait that ran out through info
+    // (every entry -1), so it needs a caller-visible info array
+    if (opt->batch && !opt->info) return -12;
     const size_t need = p.atom_bytes() + p.kpoint_bytes(N_G, opt->mode);
     if (need > (size_t)HS_STATIC_SCRATCH_BYTES) {   // host-side check, before any device call
         hs::set_error(HS_ERR_WORKSPACE, "hs_build_static: the build needs " + std::to_string(need) +

@@ -194,6 +194,10 @@ def test_batch_option_checks():
     opt.tuning = ctypes.pointer(t)
     assert lib.hs_build_ex(*[FAKE] * 6, 2, 4, 8, FAKE, FAKE, ctypes.byref(opt)) == -12
     opt = Bd.hs_options()
+    opt.batch = 1   # batched launch without an info array to report a timed-out wait
+    assert lib.hs_build_ex(*[FAKE] * 6, 2, 4, 8, FAKE, FAKE, ctypes.byref(opt)) == -12
+    assert lib.hs_build_static(*[FAKE] * 6, 2, 4, 8, FAKE, FAKE, ctypes.byref(opt)) == -12
+    opt = Bd.hs_options()
     opt.batch = 2
     assert lib.hs_ctx_build(FAKE, FAKE, FAKE, 8, FAKE, FAKE, ctypes.byref(opt)) == -7
 
