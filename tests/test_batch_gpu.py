@@ -170,3 +170,34 @@ def test_batching_workload_sampled():
     assert np.array_equal(info, _expected_info(p))
     Hr = O.hamiltonian_columns(p.A, p.B, p.T_AA, p.T_AB, p.T_BB, p.nl, cols)
     assert _rel(Hb, Hr) <= TOL
+
+
+def test_autotune_cache_round_trip(tmp_path):
+    """The tuner's JSON cache: a first call measures and stores, a second
+    reads the same choices back without measuring, a new N_L is measured
+    alone and added, and a build with the cached table is bitwise the one
+    with the measured table."""
+    import json
+    from paper_1611_00606_amd.tuning import autotune
+    cache = str(tmp_path / "tune.json")
+    n_g = 600
+    t1, r1 = autotune([16, 81], n_g, reps=1, cache=cache)
+    assert all(r1[v]["ms"] is not None for v in (16, 81))
+    stored = json.load(open(cache))
+    assert sorted(k.split("/")[-1] for k in stored) == ["N_L=16", "N_L=81"]
+    assert all(f"N_G={n_g}" in k for k in stored)
+    t2, r2 = autotune([81, 16], n_g, reps=1, cache=cache)
+    assert all(r2[v]["ms"] is None for v in (16, 81))   # read back, not measured
+    assert bytes(t1.cfg) == bytes(t2.cfg)
+    t3, r3 = autotune([16, 49, 81], n_g, reps=1, cache=cache)
+    assert r3[49]["ms"] is not None and r3[16]["ms"] is None and r3[81]["ms"] is None
+    assert len(json.load(open(cache))) == 3
+    assert t3.cfg[16] == t1.cfg[16] and t3.cfg[81] == t1.cfg[81]
+    p = make_problem(3, [16, 81, 49], n_g, seed=31, fail_atoms=[1])
+    ra = _run(p, batch=1, tuning=t3)
+    Ha, Sa, ia = ra.results()
+    from paper_1611_00606_amd.tuning import tuning_from_table
+    rb = _run(p, batch=1, tuning=tuning_from_table({v: int(t3.cfg[v]) for v in (16, 49, 81)}))
+    Hb, Sb, ib = rb.results()
+    assert np.array_equal(Ha, Hb) and np.array_equal(Sa, Sb) and np.array_equal(ia, ib)
+    assert _rel(Ha, O.hamiltonian(p.A, p.B, p.T_AA, p.T_AB, p.T_BB, p.nl)) <= TOL
