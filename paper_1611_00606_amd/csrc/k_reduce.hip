@@ -29,28 +29,11 @@ namespace hs {
 
 namespace {
 
-// Tile shape of the reductions (overridable at build time for tuning sweeps).
-#ifndef HS_RED_BM
-#define HS_RED_BM 128
-#endif
-#ifndef HS_RED_BN
-#define HS_RED_BN 128
-#endif
-#ifndef HS_RED_BK
-#define HS_RED_BK 16
-#endif
-#ifndef HS_RED_WM
-#define HS_RED_WM 2
-#endif
-#ifndef HS_RED_WN
-#define HS_RED_WN 4
-#endif
-#ifndef HS_RED_BAND
-#define HS_RED_BAND 4
-#endif
-using RedCfg = TileCfg<HS_RED_BM, HS_RED_BN, HS_RED_BK, HS_RED_WM, HS_RED_WN>;
-static_assert(HS_RED_BM == HS_RED_BN, "lower-triangle tiling needs square tiles");
-constexpr int BAND = HS_RED_BAND;   // tile columns per band of the tile order
+// Tile shape of the reductions: 128 x 128 outputs, stages of 16 contraction
+// rows, 8 waves as 2 x 4 (64 x 32 complex outputs each).
+using RedCfg = TileCfg<128, 128, 16, 2, 4>;
+static_assert(RedCfg::BM == RedCfg::BN, "lower-triangle tiling needs square tiles");
+constexpr int BAND = 4;   // tile columns per band of the tile order
 
 struct RedArgs {
     const double2 *A, *B, *Z, *W;

@@ -42,29 +42,6 @@
 #include "hs_internal.h"
 #include "zmfma_tile.h"
 
-#ifndef HS_SPLIT_NSL
-#define HS_SPLIT_NSL 4
-#endif
-#ifndef HS_SPLIT_BITS1
-#define HS_SPLIT_BITS1 8
-#endif
-#ifndef HS_SPLIT_BITS
-#define HS_SPLIT_BITS 9
-#endif
-#ifndef HS_SPLIT_FLUSH
-#define HS_SPLIT_FLUSH 4
-#endif
-#ifndef HS_SPLIT_WM
-#define HS_SPLIT_WM 2
-#endif
-#ifndef HS_SPLIT_WN
-#define HS_SPLIT_WN 4
-#endif
-// 1: slices move global -> LDS with direct 16-byte loads; 0: through registers
-#ifndef HS_SPLIT_DIRECT
-#define HS_SPLIT_DIRECT 1
-#endif
-
 namespace hs {
 
 namespace {
@@ -72,9 +49,9 @@ namespace {
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int NSL = HS_SPLIT_NSL;      // slices per value
-constexpr int SBITS1 = HS_SPLIT_BITS1; // bits of the first slice
-constexpr int SBITS = HS_SPLIT_BITS;   // bits of the other slices
+constexpr int NSL = 4;                 // slices per value
+constexpr int SBITS1 = 8;              // bits of the first slice
+constexpr int SBITS = 9;               // bits of the other slices
 constexpr int NLEV = NSL;              // levels c = 2 .. NSL + 1
 static_assert(SBITS1 <= 10 && SBITS <= 10, "slices must be integers FP16 holds exactly");
 
@@ -176,13 +153,13 @@ k_slice(SliceSrc src, int K, int n_g, int groups) {
 
 constexpr int SBM = 64;                 // tile rows (g')
 constexpr int SBN = 64;                 // tile cols (g)
-constexpr int SWM = HS_SPLIT_WM, SWN = HS_SPLIT_WN;
+constexpr int SWM = 2, SWN = 4;         // waves
 constexpr int SNT = 64 * SWM * SWN;
 constexpr int SWTM = SBM / SWM, SWTN = SBN / SWN;   // wave tile
 constexpr int STM = SWTM / 16;          // 16-row blocks per wave
 constexpr int STN = SWTN / 16;          // 16-col blocks per wave
 constexpr int SGRP = 4;                 // groups (of 4 complex rows) per stage = 16 rows
-constexpr int FLUSH = HS_SPLIT_FLUSH;   // stages per flush
+constexpr int FLUSH = 4;                // stages per flush
 // exactness of the two leading levels between flushes (2 * 16 * FLUSH real
 // products per pair): level 2 one pair of |sig_1| <= 2^b1, level 3 two
 // pairs of |sig_1| <= 2^b1 times |sig_2| <= 2^(b-1)
@@ -193,7 +170,6 @@ static_assert(SBITS1 + SBITS - 1 + 1 + ilog2(32 * FLUSH) <= 24, "level 3 exact i
 constexpr int SBAND = 8;
 // LDS per operand per stage: NSL slices x SGRP groups x 64 columns x 16 B
 constexpr int LDS_OP = NSL * SGRP * 64;   // in units of 16 B
-[[maybe_unused]] constexpr int LD_ITEMS = (LDS_OP + SNT - 1) / SNT;
 static_assert(SBM == 64 && SBN == 64, "loader assumes 64-column tiles");
 static_assert(SWTM % 16 == 0 && SWTN % 16 == 0, "wave tiling");
 
@@ -256,7 +232,6 @@ __device__ __forceinline__ void split_segment(const SplitSeg sg, int n_g, int gr
 
     const long long plane = (long long)groups * n_g;   // 16-byte items per slice
     const int nstage = groups / SGRP;
-#if HS_SPLIT_DIRECT
     // direct global -> LDS loads, 64 columns each: wave w loads group w % 4
     // of every slice of operand w / 4 (P for waves 0-3, Q for 4-7); columns
     // past the edge read the last column (they only feed outputs past N_G)
@@ -275,52 +250,6 @@ __device__ __forceinline__ void split_segment(const SplitSeg sg, int n_g, int gr
                 reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(rows + s * plane) + ldvo),
                 dst + s * SGRP * 64, 16, 0, 0);
     };
-#else
-    // loader: NSL*SGRP*64 16-byte items per operand per stage, item
-    // id -> (slice, group, column) = (id / 256, (id / 64) % 4, id % 64); each
-    // thread moves up to LD_ITEMS of them (indices clamped, extra ones unused)
-    const int col = tid & 63;
-    const int pm = m0 + col, qn = n0 + col;
-    const bool pok = pm < n_g, qok = qn < n_g;
-    const int pmc = pok ? pm : n_g - 1, qnc = qok ? qn : n_g - 1;
-    const uint4 *Pg = reinterpret_cast<const uint4 *>(sg.P);
-    const uint4 *Qg = reinterpret_cast<const uint4 *>(sg.Q);
-    uint4 rp[LD_ITEMS], rq[LD_ITEMS];
-    auto fetch = [&](int st) {
-        const int st_c = st < nstage ? st : nstage - 1;   // clamped (unused past the end)
-#pragma unroll
-        for (int j = 0; j < LD_ITEMS; ++j) {
-            const int idv = tid + j * SNT;
-            const int id = idv < LDS_OP ? idv : LDS_OP - 1;
-            const int s = id >> 8, gi = (id >> 6) & 3;
-            const long long g = (long long)st_c * SGRP + gi;
-            rp[j] = Pg[s * plane + g * n_g + pmc];
-            rq[j] = Qg[s * plane + g * n_g + qnc];
-        }
-    };
-    // per-component selects (an aggregate select becomes an address select
-    // that sends the staging registers to scratch)
-    auto stash = [&](int buf) {
-        uint4 *lp = lds + buf * 2 * LDS_OP;
-        uint4 *lq = lp + LDS_OP;
-#pragma unroll
-        for (int j = 0; j < LD_ITEMS; ++j) {
-            const int id = tid + j * SNT;
-            if (id >= LDS_OP) continue;
-            uint4 a, b;
-            a.x = pok ? rp[j].x : 0u;
-            a.y = pok ? rp[j].y : 0u;
-            a.z = pok ? rp[j].z : 0u;
-            a.w = pok ? rp[j].w : 0u;
-            b.x = qok ? rq[j].x : 0u;
-            b.y = qok ? rq[j].y : 0u;
-            b.z = qok ? rq[j].z : 0u;
-            b.w = qok ? rq[j].w : 0u;
-            lp[id] = a;
-            lq[id] = b;
-        }
-    };
-#endif
 
     // column scales of this lane's accumulator rows (g') and columns (g),
     // with the 2^-2b1 weight of the first level folded in
@@ -414,7 +343,6 @@ __device__ __forceinline__ void split_segment(const SplitSeg sg, int n_g, int gr
 
     clear();
     if (nstage == 0) return;
-#if HS_SPLIT_DIRECT
     issue(lds, 0);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
@@ -432,19 +360,6 @@ __device__ __forceinline__ void split_segment(const SplitSeg sg, int n_g, int gr
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
     }
-#else
-    fetch(0);
-    stash(0);
-    __syncthreads();
-    for (int st = 0; st < nstage; ++st) {
-        fetch(st + 1);
-        const uint4 *lp = lds + (st & 1) * 2 * LDS_OP;
-        compute(lp, lp + LDS_OP);
-        stash((st + 1) & 1);
-        if ((st + 1) % FLUSH == 0 || st + 1 == nstage) flush();
-        __syncthreads();
-    }
-#endif
 }
 
 __global__ void __launch_bounds__(SNT)
@@ -514,61 +429,37 @@ k_split_reduce(SplitArgs args) {
 // most 28544 < 2^15 per real product, so a level stays exact for 2^16 real
 // products: the accumulators are combined in FP64 (Horner, scaled by
 // 2^(eP + eQ - 14)) only at the end of each (P, Q) segment and every 32768
-// complex rows, and added to the output tile in memory (written by the first
-// flush, read-modified-written by later ones, by the same thread in a fixed
-// order: deterministic). No FP64 accumulator is held during the K loop.
+// complex rows, into an FP64 accumulator tile held in LDS across the
+// segments of the output (each element read-modified-written by the lane
+// that owns it, in a fixed order: deterministic); each output element is
+// stored to memory once, after its last segment. No FP64 work sits in the K
+// loop.
 //
 // Errors left: remainders (2^-36 of the column maxima on each side),
 // dropped pairs (s + t = 7: four pairs of |sig sig'| <= 2^12 at 2^-49, i.e.
 // 2^-35), FP64 rounding.
 //
-// Tiles: 64 x 64, HS_SPLIT8_WAVES waves (8: 2 x 4 waves of 32 x 16; 4: 2 x 2
-// waves of 32 x 32). A stage is 32 complex rows (one MFMA K step of 64
-// int8). Operand slices go straight from global memory to LDS (16-byte
-// direct loads of 64 columns; 40 per stage) through a ring of 40 KiB LDS
-// buffers, so no staging registers are needed.
-
-#ifndef HS_SPLIT8_WAVES
-#define HS_SPLIT8_WAVES 8
-#endif
-// LDS buffers in the load ring (2: next stage in flight; 3: two stages)
-#ifndef HS_SPLIT8_RING
-#define HS_SPLIT8_RING 2
-#endif
-#ifndef HS_SPLIT8_BAND
-#define HS_SPLIT8_BAND 8
-#endif
-// tile rows: 64 (square 64 x 64 tiles) or 128 (128 x 64 halves of 128 x 128
-// lower-triangle super tiles)
-#ifndef HS_SPLIT8_BM
-#define HS_SPLIT8_BM 64
-#endif
+// Tiles: 64 x 64, 8 waves (2 x 4 waves of 32 x 16). A stage is 32 complex
+// rows (one MFMA K step of 64 int8). Operand slices go straight from global
+// memory to LDS (16-byte direct loads of 64 columns; 40 per stage) through
+// two 40 KiB LDS buffers (the next stage loads while the current one is
+// multiplied), so no staging registers are needed; with the 64 KiB
+// accumulator tile one block takes 144 KiB of the CU's 160 KiB.
 
 typedef int i4 __attribute__((ext_vector_type(4)));
 typedef unsigned short us2 __attribute__((ext_vector_type(2)));
 
 constexpr int NSL8 = 5;                  // slices per value
 constexpr int NLEV8 = 5;                 // levels c = 2 .. 6
-constexpr int B8M = HS_SPLIT8_BM;        // tile rows (g')
-constexpr int B8 = 64;                   // tile cols (g)
-constexpr int NW8 = HS_SPLIT8_WAVES;
-#ifndef HS_SPLIT8_WM
-#define HS_SPLIT8_WM (HS_SPLIT8_BM == 128 ? 8 : 2)
-#endif
-constexpr int W8M = HS_SPLIT8_WM, W8N = NW8 / W8M;   // waves
-constexpr int NT8 = 64 * NW8;
-constexpr int T8M = B8M / W8M / 16, T8N = B8 / W8N / 16;   // 16x16 blocks per wave
+constexpr int B8 = 64;                   // tile rows (g') and columns (g)
+constexpr int W8M = 2, W8N = 4;          // waves
+constexpr int NT8 = 64 * W8M * W8N;
+constexpr int T8M = B8 / W8M / 16, T8N = B8 / W8N / 16;   // 16x16 blocks per wave
 constexpr int GRP8 = 4;                  // groups of 8 complex rows per stage = 32 rows
-constexpr int P8_ITEMS = NSL8 * GRP8 * B8M;   // 16-byte items per stage
-constexpr int OP8_ITEMS = NSL8 * GRP8 * B8;
-constexpr int BUF8 = P8_ITEMS + OP8_ITEMS;
-static_assert(B8M == 64 || (B8M == 128 && NW8 == 8), "128-row tiles use 8 waves");
+constexpr int OP8_ITEMS = NSL8 * GRP8 * B8;   // 16-byte items per operand and stage
+constexpr int BUF8 = 2 * OP8_ITEMS;
 constexpr int FLUSH8 = 1024;                  // stages (32768 complex rows) per flush
-constexpr int BAND8 = HS_SPLIT8_BAND;
-constexpr int RING8 = HS_SPLIT8_RING;
-static_assert(NW8 == 4 || NW8 == 8, "4 or 8 waves");
-static_assert(RING8 == 2 || RING8 == 3, "2 or 3 LDS buffers");
-static_assert(T8M >= 1 && T8N >= 1, "wave tiling");
+constexpr int BAND8 = 8;
 static_assert((long long)FLUSH8 * 64 * 28544 < (1LL << 31), "levels exact in INT32");
 
 // exponent e with column max * 128/127 < 2^e (0 for an all-zero column)
@@ -635,9 +526,15 @@ __device__ __forceinline__ unsigned im_pairs(unsigned d) {
     return __builtin_bit_cast(unsigned, h);
 }
 
+// One (P, Q) segment into the tile's FP64 accumulator acc (64 x 64 complex
+// values in LDS, element (r, c) at r * 64 + c; each element is only ever
+// touched by the lane that owns it in the MFMA layout, so no barrier is
+// needed around it). first: the segment's first flush writes instead of
+// adding. The segment is taken by value for the same reason as
+// split_segment.
 __device__ __forceinline__ void split8_segment(const Split8Seg sg, int n_g, int groups, int m0,
-                                               int n0, bool first, double2 *out, uint4 *bufs0,
-                                               uint4 *bufs1, uint4 *bufs2) {
+                                               int n0, bool first, double2 *acc, uint4 *bufs0,
+                                               uint4 *bufs1) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -645,53 +542,27 @@ __device__ __forceinline__ void split8_segment(const Split8Seg sg, int n_g, int 
     const long long plane = (long long)groups * n_g;
     const int nstage = groups / GRP8;
 
-    // direct loads of stage st into buf, 64 columns each. 64-row tiles (40
-    // loads): with 8 waves wave w loads group w % 4 of every slice of operand
-    // w / 4, with 4 waves group w of both operands. 128-row tiles (60
-    // loads): wave w loads group w / 2, columns 64 (w % 2) .. of every P
-    // slice, and the Q (slice, group) pairs w, w + 8, w + 16.
-    constexpr int OPS_PER_WAVE = NW8 == 8 ? 1 : 2;
-    constexpr int LOADS_PER_WAVE = B8M == 128 ? NSL8 + 3 : NSL8 * OPS_PER_WAVE;
-    const int grp_w = B8M == 128 ? wave >> 1 : wave % GRP8;
-    const int half_w = B8M == 128 ? wave & 1 : 0;
-    const int op0 = NW8 == 8 && B8M == 64 ? wave / GRP8 : 0;
-    int pc = m0 + half_w * 64 + lane;
-    pc = pc < n_g ? pc : n_g - 1;
-    int qc = n0 + lane;
-    qc = qc < n_g ? qc : n_g - 1;
-    // per-lane byte offsets (32-bit) from wave-uniform row bases: the loads
+    // direct loads of stage st into buf, 64 columns each (40 loads): wave w
+    // loads group w % 4 of every slice of operand w / 4 (P for waves 0-3, Q
+    // for 4-7); columns past the edge read the last column (they only feed
+    // outputs past N_G, which are not stored)
+    static_assert(NT8 == 512, "the loader assumes 8 waves");
+    const int grp_w = wave % GRP8;
+    const int op_w = wave / GRP8;
+    int ldc = (op_w == 0 ? m0 : n0) + lane;
+    ldc = ldc < n_g ? ldc : n_g - 1;
+    // per-lane byte offset (32-bit) from wave-uniform row bases: the loads
     // then take the scalar-base form and need no 64-bit address registers
-    const unsigned pvo = (unsigned)pc * 16u, qvo = (unsigned)qc * 16u;
-    auto ld = [&](const uint4 *row, unsigned vo, uint4 *dst) __attribute__((always_inline)) {
-        __builtin_amdgcn_global_load_lds(
-            reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(row) + vo), dst, 16, 0, 0);
-    };
+    const unsigned ldvo = (unsigned)ldc * 16u;
+    const uint4 *ldrows = op_w == 0 ? sg.P : sg.Q;
     auto issue = [&](uint4 *buf, int st) __attribute__((always_inline)) {
-        if constexpr (B8M == 128) {
+        const uint4 *rows = ldrows + (long long)(st * GRP8 + grp_w) * n_g;
+        uint4 *dst = buf + op_w * OP8_ITEMS + grp_w * B8;
 #pragma unroll
-            for (int s = 0; s < NSL8; ++s)
-                ld(sg.P + s * plane + (long long)(st * GRP8 + grp_w) * n_g, pvo,
-                   buf + (s * GRP8 + grp_w) * B8M + half_w * 64);
-#pragma unroll
-            for (int it = 0; it < 3; ++it) {
-                const int j = wave + 8 * it;
-                if (j < NSL8 * GRP8) {
-                    const int s = j / GRP8, grp = j % GRP8;
-                    ld(sg.Q + s * plane + (long long)(st * GRP8 + grp) * n_g, qvo,
-                       buf + P8_ITEMS + (s * GRP8 + grp) * B8);
-                }
-            }
-        } else {
-#pragma unroll
-            for (int o = 0; o < OPS_PER_WAVE; ++o) {
-                const int op = op0 + o;
-                const uint4 *rows = (op == 0 ? sg.P : sg.Q) + (long long)(st * GRP8 + grp_w) * n_g;
-                const unsigned vo = op == 0 ? pvo : qvo;
-                uint4 *dst = buf + op * P8_ITEMS + grp_w * B8;
-#pragma unroll
-                for (int s = 0; s < NSL8; ++s) ld(rows + s * plane, vo, dst + s * GRP8 * B8);
-            }
-        }
+        for (int s = 0; s < NSL8; ++s)
+            __builtin_amdgcn_global_load_lds(
+                reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(rows + s * plane) + ldvo),
+                dst + s * GRP8 * B8, 16, 0, 0);
     };
 
     i4 lre[T8M][T8N][NLEV8], lim[T8M][T8N][NLEV8];
@@ -709,13 +580,13 @@ __device__ __forceinline__ void split8_segment(const Split8Seg sg, int n_g, int 
     const int lg = lane >> 4, lc = lane & 15;
     auto compute = [&](const uint4 *buf) __attribute__((always_inline)) {
         const uint4 *lp = buf;
-        const uint4 *lq = buf + P8_ITEMS;
+        const uint4 *lq = buf + OP8_ITEMS;
         i4 a[T8M][NSL8];
 #pragma unroll
         for (int s = 0; s < NSL8; ++s)
 #pragma unroll
             for (int i = 0; i < T8M; ++i)
-                a[i][s] = __builtin_bit_cast(i4, lp[(s * GRP8 + lg) * B8M + wm * (B8M / W8M) + i * 16 + lc]);
+                a[i][s] = __builtin_bit_cast(i4, lp[(s * GRP8 + lg) * B8 + wm * (B8 / W8M) + i * 16 + lc]);
 #pragma unroll
         for (int t = 0; t < NSL8; ++t)
 #pragma unroll
@@ -738,86 +609,62 @@ __device__ __forceinline__ void split8_segment(const Split8Seg sg, int n_g, int 
                 }
             }
     };
-    // levels -> FP64, scaled, into the output tile (lower triangle only)
+    // levels -> FP64, scaled, into the accumulator tile
     auto flush = [&](bool write) __attribute__((always_inline)) {
 #pragma unroll
         for (int j = 0; j < T8N; ++j) {
-            const int g = n0 + wn * (B8 / W8N) + j * 16 + lc;
+            const int c = wn * (B8 / W8N) + j * 16 + lc;
+            const int g = n0 + c;
             const int eq = col_exp8(sg.mQ, g < n_g ? g : n_g - 1);
 #pragma unroll
             for (int i = 0; i < T8M; ++i)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int gp = m0 + wm * (B8M / W8M) + i * 16 + 4 * lg + v;
-                    if (gp < n_g && g <= gp) {
-                        const double w = ldexp(1.0, col_exp8(sg.mP, gp) + eq - 14);
-                        double tr = (double)lre[i][j][NLEV8 - 1][v];
-                        double ti = (double)lim[i][j][NLEV8 - 1][v];
+                    const int r = wm * (B8 / W8M) + i * 16 + 4 * lg + v;
+                    const int gp = m0 + r;
+                    const double w = ldexp(1.0, col_exp8(sg.mP, gp < n_g ? gp : n_g - 1) + eq - 14);
+                    double tr = (double)lre[i][j][NLEV8 - 1][v];
+                    double ti = (double)lim[i][j][NLEV8 - 1][v];
 #pragma unroll
-                        for (int c = NLEV8 - 2; c >= 0; --c) {
-                            tr = fma(tr, 1.0 / 128.0, (double)lre[i][j][c][v]);
-                            ti = fma(ti, 1.0 / 128.0, (double)lim[i][j][c][v]);
-                        }
-                        double2 *o = out + (long long)gp * n_g + g;
-                        double2 r = double2{tr * w, ti * w};
-                        if (!write) {
-                            const double2 prev = *o;
-                            r.x += prev.x;
-                            r.y += prev.y;
-                        }
-                        *o = r;
+                    for (int lv = NLEV8 - 2; lv >= 0; --lv) {
+                        tr = fma(tr, 1.0 / 128.0, (double)lre[i][j][lv][v]);
+                        ti = fma(ti, 1.0 / 128.0, (double)lim[i][j][lv][v]);
                     }
+                    double2 *e = acc + r * B8 + c;
+                    double2 x = double2{tr * w, ti * w};
+                    if (!write) {
+                        const double2 prev = *e;
+                        x.x += prev.x;
+                        x.y += prev.y;
+                    }
+                    *e = x;
                 }
         }
         clear();
     };
 
     clear();
-    // Ring of RING8 LDS buffers: stage st lives in buf[st % RING8]; the
-    // loads of the next RING8 - 1 stages are in flight while st is computed.
-    // Each wave issues LOADS_PER_WAVE direct loads per stage, so waiting
-    // until at most (RING8 - 2) * LOADS_PER_WAVE of them are outstanding
-    // completes the oldest stage in flight.
-    auto bufp = [&](int st) __attribute__((always_inline)) {
-        const int r = st % RING8;
-        return r == 0 ? bufs0 : r == 1 ? bufs1 : bufs2;
-    };
-    auto wait_oldest = [&](bool more_in_flight) __attribute__((always_inline)) {
-        // with 3 buffers: at most the newest stage's loads may stay in flight
-        // (a wave issues at most LOADS_PER_WAVE per stage; fewer only waits
-        // longer)
-        if (RING8 == 3 && more_in_flight) {
-            static_assert(LOADS_PER_WAVE == 5 || LOADS_PER_WAVE == 8 || LOADS_PER_WAVE == 10,
-                          "waitcnt immediates");
-            if constexpr (LOADS_PER_WAVE == 5) asm volatile("s_waitcnt vmcnt(5)" ::: "memory");
-            else if constexpr (LOADS_PER_WAVE == 8) asm volatile("s_waitcnt vmcnt(7)" ::: "memory");
-            else asm volatile("s_waitcnt vmcnt(10)" ::: "memory");
-        } else {
-            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        }
-    };
-    for (int k = 0; k < RING8 - 1 && k < nstage; ++k) issue(bufp(k), k);
-    wait_oldest(RING8 == 3 && nstage > 1);
+    if (nstage == 0) return;
+    issue(bufs0, 0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
-    bool fresh = first;
     for (int c0 = 0; c0 < nstage; c0 += FLUSH8) {
         const int c1 = nstage < c0 + FLUSH8 ? nstage : c0 + FLUSH8;
         for (int st = c0; st < c1; ++st) {
-            const int nx = st + RING8 - 1;
             // the buffer being computed and the one being loaded are
             // distinct: saying so (restrict) keeps the compiler from waiting
             // for the direct loads before every LDS read of the stage
             auto stage = [&](const uint4 *__restrict__ cur, uint4 *__restrict__ nxt)
                              __attribute__((always_inline)) {
-                if (nx < nstage) issue(nxt, nx);
+                if (st + 1 < nstage) issue(nxt, st + 1);
                 compute(cur);
             };
-            stage(bufp(st), bufp(nx));
-            wait_oldest(RING8 == 3 && st + 2 < nstage);
+            stage((st & 1) ? bufs1 : bufs0, (st & 1) ? bufs0 : bufs1);
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
             __syncthreads();
         }
-        flush(fresh);
-        fresh = false;
+        flush(first);
+        first = false;
     }
 }
 
@@ -825,7 +672,7 @@ __global__ void __launch_bounds__(NT8)
 k_split8_reduce(Split8Args args) {
     __shared__ uint4 bufA[BUF8];
     __shared__ uint4 bufB[BUF8];
-    __shared__ uint4 bufC[RING8 == 3 ? BUF8 : 1];
+    __shared__ double2 acc[B8 * B8];   // the tile's FP64 sums across segments
 
     int b = blockIdx.x;
     const bool isH = b < args.ntri8;
@@ -834,31 +681,36 @@ k_split8_reduce(Split8Args args) {
     const int t = (b % 8) * per_xcd + b / 8;
     if (t >= args.ntri) return;
     int ti, tj;
+    sband_tile(t, args.nt, ti, tj, BAND8);
+    if (ti < 0) return;
     const int n_g = args.n_g;
-    int m0, n0;
-    if constexpr (B8M == 128) {   // t: (super tile, half)
-        sband_tile(t >> 1, args.nt, ti, tj, BAND8);
-        if (ti < 0) return;
-        m0 = ti * 128;
-        n0 = tj * 128 + (t & 1) * 64;
-        if (n0 >= n_g) return;
+    const int m0 = ti * B8, n0 = tj * B8;
+
+    if (isH) {
+        const Split8Seg h0 = args.h[0], h1 = args.h[1], h2 = args.h[2];
+        split8_segment(h0, n_g, args.groups, m0, n0, true, acc, bufA, bufB);
+        split8_segment(h1, n_g, args.groups, m0, n0, false, acc, bufA, bufB);
+        split8_segment(h2, n_g, args.groups, m0, n0, false, acc, bufA, bufB);
     } else {
-        sband_tile(t, args.nt, ti, tj, BAND8);
-        if (ti < 0) return;
-        m0 = ti * B8;
-        n0 = tj * B8;
+        const Split8Seg s0 = args.s[0], s1 = args.s[1];
+        split8_segment(s0, n_g, args.groups, m0, n0, true, acc, bufA, bufB);
+        split8_segment(s1, n_g, args.groups, m0, n0, false, acc, bufA, bufB);
     }
 
     double2 *out = isH ? args.H : args.S;
-    if (isH) {
-        const Split8Seg h0 = args.h[0], h1 = args.h[1], h2 = args.h[2];
-        split8_segment(h0, n_g, args.groups, m0, n0, true, out, bufA, bufB, bufC);
-        split8_segment(h1, n_g, args.groups, m0, n0, false, out, bufA, bufB, bufC);
-        split8_segment(h2, n_g, args.groups, m0, n0, false, out, bufA, bufB, bufC);
-    } else {
-        const Split8Seg s0 = args.s[0], s1 = args.s[1];
-        split8_segment(s0, n_g, args.groups, m0, n0, true, out, bufA, bufB, bufC);
-        split8_segment(s1, n_g, args.groups, m0, n0, false, out, bufA, bufB, bufC);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave % W8M, wn = wave / W8M;
+#pragma unroll
+    for (int j = 0; j < T8N; ++j) {
+        const int g = n0 + wn * (B8 / W8N) + j * 16 + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < T8M; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = wm * (B8 / W8M) + i * 16 + 4 * (lane >> 4) + v;
+                const int gp = m0 + r;
+                if (gp < n_g && g <= gp) out[(long long)gp * n_g + g] = acc[r * B8 + (g - n0)];
+            }
     }
 }
 
@@ -934,8 +786,8 @@ hipError_t launch_split8_reduce(int K, int n_g, const SliceView (&hseg)[3][2],
     a.S = S;
     a.n_g = n_g;
     a.groups = (K + 31) / 32 * GRP8;
-    a.nt = (n_g + B8M - 1) / B8M;
-    a.ntri = a.nt * (a.nt + 1) / 2 * (B8M / B8);   // blocks per output
+    a.nt = (n_g + B8 - 1) / B8;
+    a.ntri = a.nt * (a.nt + 1) / 2;   // blocks per output
     a.ntri8 = (a.ntri + 7) / 8 * 8;
     hipLaunchKernelGGL(k_split8_reduce, dim3(2 * a.ntri8), dim3(NT8), 0, st, a);
     return hipGetLastError();
