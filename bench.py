@@ -56,6 +56,8 @@ TRAFFIC_RECORDS = {
                      "paper_1611_00606_amd/csrc/k_reduce.hip"]),
     "k_split_reduce": ("k_split_reduces_precision_ng8000.md", ["paper_1611_00606_amd/csrc/k_split.hip"]),
     "k_split8_reduce": ("k_split_reduces_precision_ng8000.md", ["paper_1611_00606_amd/csrc/k_split.hip"]),
+    "k_split_reduce_bf16": ("k_split_reduces_precision_ng8000.md",
+                            ["paper_1611_00606_amd/csrc/k_split.hip"]),
 }
 TRAFFIC_UNIT = ("HBM bytes per launch: rocprofv3 TCC_EA0 read requests by size (32, 64, 128 B) "
                 "and write requests by size (32, 64 B), one launch on this workload")
@@ -271,6 +273,12 @@ SPLIT_MODES = {
             per_fp64=SPLIT_I8_PER_FP64, peak=INT8_MFMA_PEAK_TOPS,
             unit="TOP/s (INT8 MFMA ops issued)",
             kernel="slicing + split reduction (phase 2..3)", phase="slice_and_reduce_HS"),
+    4: dict(name="split_bf16", traffic_kernel="k_split_reduce_bf16", slice_bytes=16.0,
+            mode="split_bf16 (the FP16 form's slices held as BF16 on BF16 MFMA: the same "
+                 "integers, exact in both formats, so the same H and S)",
+            per_fp64=SPLIT_F16_PER_FP64, peak=FP16_MFMA_PEAK_TFLOPS,
+            unit="TFLOP/s (BF16 MFMA flops issued)",
+            kernel="slicing + split reduction (phase 2..3)", phase="slice_and_reduce_HS"),
     3: dict(name="fp64_3m", traffic_kernel="k_reduce_3m", slice_bytes=16.0,
             mode="fp64_3m (complex FP64 with 3 real MFMA products per complex product: "
                  "T1 = pr qr, T2 = pi qi, T3 = (pr - pi)(qr + qi); Re = T1 + T2, Im = T3 - T1 + T2)",
@@ -305,7 +313,7 @@ def split_bench(p, steps: int, warmup: int, fp64_ms: float, hip, mode: int, n_co
     issued = m["per_fp64"] * reduction_flops(p.nl, p.N_G) / (ph[2] * 1e-3) / 1e12
     # split forms read six sliced operands (16 B per complex element for the
     # FP16 slices, 10 B for the INT8 ones); the 3M form the four FP64 ones
-    alg_bytes = reduction_bytes(p.K, p.N_G, m["slice_bytes"], 6 if mode in (1, 2) else 4)
+    alg_bytes = reduction_bytes(p.K, p.N_G, m["slice_bytes"], 6 if mode in (1, 2, 4) else 4)
     traffic = measured_traffic(p.name, m["traffic_kernel"])
     return {
         "mode": m["mode"],
@@ -458,6 +466,10 @@ def serving_bench(seed: int, sizes, data, n_slots: int = 4, arena_gb: float = 24
         offered.append((len(reqs) - 1) / arrivals[-1])
         runs.append(loop.run([dict(r, id=r["id"] + 10000 * j) for r in reqs], arrivals))
         peak = max(peak, loop.peak_bytes)
+    # capacity: all requests at once (the stream is no longer rate-limited
+    # by its arrivals; builds/s is what the slots and the arena sustain)
+    sat = loop.run([dict(r, id=r["id"] + 30000) for r in reqs], [0.0] * len(reqs))
+    sat_span = max(r["done"] for r in sat) - min(r["arrival"] for r in sat)
     # untimed check pass: n_check requests in one burst, seeded columns kept
     order = np.argsort(sizes)
     chk = [int(order[0]), int(order[-1])]
@@ -487,7 +499,7 @@ def serving_bench(seed: int, sizes, data, n_slots: int = 4, arena_gb: float = 24
     out["latency_samples"] = len(reqs) * streams
     out["offered_rate_per_s"] = [round(x, 3) for x in offered]
     out.update({
-        "mode": {0: "fp64", 1: "split_f16", 2: "split_i8", 3: "fp64_3m"}[mode],
+        "mode": {0: "fp64", 1: "split_f16", 2: "split_i8", 3: "fp64_3m", 4: "split_bf16"}[mode],
         "workload": "64 requests, N_A=64 atoms, N_L=64, N_G uniform in [1500, 9000], each with "
                     "its own seeded A, B in pinned host memory, Poisson arrivals",
         "arrival_rate_per_s": rate,   # nominal Poisson rate; offered_rate_per_s is realized
@@ -499,6 +511,8 @@ def serving_bench(seed: int, sizes, data, n_slots: int = 4, arena_gb: float = 24
                       f"bypass (a waiting request is passed at most {max_bypass} times)"),
         "arena_gb": arena_gb,
         "peak_arena_gb": peak / 1e9,
+        "saturated_builds_per_s": len(sat) / sat_span,
+        "saturated_tflops_fp64_equiv": sum(flops_of(r["N_G"]) for r in sat) / sat_span / 1e12,
         "checked_requests": chk,
         "max_rel_err_H": None,
         "max_rel_err_S": None,
@@ -707,9 +721,9 @@ def main():
                     help="skip the serving-form measurement (k-point builds/s, p50/p99)")
     ap.add_argument("--no-split", action="store_true",
                     help="skip the split-precision and 3M measurements")
-    ap.add_argument("--split-modes", default="1,2,3",
+    ap.add_argument("--split-modes", default="1,2,3,4",
                     help="alternative reduction modes to measure (1 = HS_SPLIT_F16, "
-                         "2 = HS_SPLIT_I8, 3 = HS_FP64_3M)")
+                         "2 = HS_SPLIT_I8, 3 = HS_FP64_3M, 4 = HS_SPLIT_BF16)")
     ap.add_argument("--per-atom", choices=["batched", "separate"], default="batched",
                     help="per-atom stage of the timed builds: the batched persistent launch with "
                          "autotuned tile shapes, or separate preparation and product launches")

@@ -108,12 +108,19 @@ enum {
  *                 bound grows from u (|pr||qi| + |pi||qr|) to
  *                 u (|pr - pi||qr + qi| + |pr||qr| + |pi||qi|) per term
  *                 (u = 2^-53, times the usual contraction-length factor).
- *                 Same workspace as HS_FP64. */
+ *                 Same workspace as HS_FP64.
+ *   HS_SPLIT_BF16 HS_SPLIT_F16 with the slices held as BF16 and multiplied on
+ *                 BF16 MFMA. The slices are integers of at most 9 bits
+ *                 (magnitude <= 256), exact in BF16 too, and their products
+ *                 accumulate exactly in FP32 either way, so H and S are
+ *                 bitwise those of HS_SPLIT_F16 (MI355X runs BF16 and FP16
+ *                 MFMA at the same dense rate). Workspace as HS_SPLIT_F16. */
 typedef enum {
     HS_FP64 = 0,
     HS_SPLIT_F16 = 1,
     HS_SPLIT_I8 = 2,
-    HS_FP64_3M = 3
+    HS_FP64_3M = 3,
+    HS_SPLIT_BF16 = 4
 } hs_mode;
 
 /* Tile shapes of the batched per-atom stage (see hs_options.batch): shape id

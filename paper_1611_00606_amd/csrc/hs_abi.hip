@@ -256,7 +256,7 @@ hipError_t enqueue_kpoint(const AtomPlan &p, const AtomBufs &ab, int n_g, int mo
         };
         for (int i = 0; i < NSPLIT; ++i) {
             e = mode == HS_SPLIT_I8 ? launch_slice8(src[i], K, n_g, st)
-                                    : launch_slice(src[i], K, n_g, st);
+                                    : launch_slice(src[i], K, n_g, st, mode == HS_SPLIT_BF16);
             if (e != hipSuccess) return e;
         }
         SliceView v[NSPLIT];
@@ -264,7 +264,8 @@ hipError_t enqueue_kpoint(const AtomPlan &p, const AtomBufs &ab, int n_g, int mo
         const SliceView hseg[3][2] = {{v[2], v[3]}, {v[3], v[2]}, {v[4], v[5]}};
         const SliceView sseg[2][2] = {{v[0], v[0]}, {v[1], v[1]}};
         e = mode == HS_SPLIT_I8 ? launch_split8_reduce(K, n_g, hseg, sseg, H, S, st)
-                                : launch_split_reduce(K, n_g, hseg, sseg, H, S, st);
+                                : launch_split_reduce(K, n_g, hseg, sseg, H, S, st,
+                                                      mode == HS_SPLIT_BF16);
     } else {
         e = launch_reduce(p.K, n_g, A, B, kb.Z, kb.W, ab.sel, ab.d, H, S, st,
                           mode == HS_FP64_3M);

@@ -68,10 +68,13 @@ const char *message_for(int status);   // the last message if it explains `statu
 int hip_fail(hipError_t e, const char *where);   // records the message, returns HS_ERR_HIP
 int check_device();                              // HS_OK on gfx950, else an error status
 int num_cus();                                   // compute units of the current device
-inline bool valid_mode(int mode) {   // HS_FP64, HS_SPLIT_F16, HS_SPLIT_I8, HS_FP64_3M
-    return mode == HS_FP64 || mode == HS_SPLIT_F16 || mode == HS_SPLIT_I8 || mode == HS_FP64_3M;
+inline bool valid_mode(int mode) {   // HS_FP64, HS_SPLIT_F16, HS_SPLIT_I8, HS_FP64_3M, HS_SPLIT_BF16
+    return mode == HS_FP64 || mode == HS_SPLIT_F16 || mode == HS_SPLIT_I8 || mode == HS_FP64_3M ||
+           mode == HS_SPLIT_BF16;
 }
-inline bool split_mode(int mode) { return mode == HS_SPLIT_F16 || mode == HS_SPLIT_I8; }
+inline bool split_mode(int mode) {
+    return mode == HS_SPLIT_F16 || mode == HS_SPLIT_I8 || mode == HS_SPLIT_BF16;
+}
 
 // Split-precision reductions (k_split.hip). A sliced operand: rows of X (or
 // of Xalt where sel[k] != 0), optionally scaled by sqrt(rscale[k]); outputs
@@ -90,11 +93,12 @@ struct SliceView {
     const unsigned long long *mx;
 };
 size_t split_slice_bytes(int K, int n_g);
-hipError_t launch_slice(const SliceSrc &src, int K, int n_g, hipStream_t st);
+// bf16: the same slices held as BF16 and multiplied on BF16 MFMA
+hipError_t launch_slice(const SliceSrc &src, int K, int n_g, hipStream_t st, bool bf16);
 // H segments (Z,B), (B,Z), (P3,W); S segments (A,A), (Bs,Bs): [segment][P or Q]
 hipError_t launch_split_reduce(int K, int n_g, const SliceView (&hseg)[3][2],
                                const SliceView (&sseg)[2][2], double2 *H, double2 *S,
-                               hipStream_t st);
+                               hipStream_t st, bool bf16);
 // INT8 form: slices S8 [5][groups][N_G][16 int8], groups = 4 * ceil(K / 32);
 // same column maxima and segments as the FP16 form.
 size_t split8_slice_bytes(int K, int n_g);

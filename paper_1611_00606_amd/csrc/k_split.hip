@@ -47,6 +47,7 @@ namespace hs {
 namespace {
 
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bh8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int NSL = 4;                 // slices per value
@@ -116,6 +117,11 @@ __device__ __forceinline__ int col_exp(const unsigned long long *mx, int n) {
 // Slices. One thread per (group of 4 complex rows, column): 8 interleaved
 // real values -> NSL slices of 8 halves, written to S[s][g][n][0..7].
 
+// BF: the slices are written as BF16 instead of FP16. Every slice is an
+// integer of magnitude <= 256, which both formats hold exactly (BF16 has 8
+// significant bits), so the two forms carry the same values and the
+// reduction's FP32 sums of their exact products are the same numbers.
+template <bool BF>
 __global__ void __launch_bounds__(256)
 k_slice(SliceSrc src, int K, int n_g, int groups) {
     const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -137,14 +143,26 @@ k_slice(SliceSrc src, int K, int n_g, int groups) {
 #pragma unroll
     for (int s = 0; s < NSL; ++s) {
         h8 h;
+        unsigned short b[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const double t = x[j] * (double)(1 << (s == 0 ? SBITS1 : SBITS));
             const double sig = rint(t);
             x[j] = t - sig;
             h[j] = (_Float16)sig;
+            // BF16 of an integer of at most 9 bits: the float's upper half, exactly
+            b[j] = (unsigned short)(__builtin_bit_cast(unsigned, (float)sig) >> 16);
         }
-        *reinterpret_cast<h8 *>(out + s * plane) = h;
+        if constexpr (BF) {
+            uint4 w;
+            w.x = b[0] | ((unsigned)b[1] << 16);
+            w.y = b[2] | ((unsigned)b[3] << 16);
+            w.z = b[4] | ((unsigned)b[5] << 16);
+            w.w = b[6] | ((unsigned)b[7] << 16);
+            *reinterpret_cast<uint4 *>(out + s * plane) = w;
+        } else {
+            *reinterpret_cast<h8 *>(out + s * plane) = h;
+        }
     }
 }
 
@@ -220,9 +238,11 @@ struct Acc64 {
     double im[STM][STN][4];
 };
 
-// One (P, Q) segment into the FP64 accumulators. The segment is taken by
+// One (P, Q) segment into the FP64 accumulators (BF: BF16 slices on BF16
+// MFMA). The segment is taken by
 // value: a reference into the by-value kernel argument would move the whole
 // argument block into scratch memory.
+template <bool BF>
 __device__ __forceinline__ void split_segment(const SplitSeg sg, int n_g, int groups, int m0,
                                               int n0, Acc64 &acc, uint4 *lds) {
     const int tid = threadIdx.x;
@@ -304,38 +324,53 @@ __device__ __forceinline__ void split_segment(const SplitSeg sg, int n_g, int gr
     const int lg = lane >> 4, lc = lane & 15;
     // slice products of one stage from LDS (P slices at lp, Q slices at lq)
     auto compute = [&](const uint4 *lp, const uint4 *lq) __attribute__((always_inline)) {
-        h8 a[STM][NSL], bre[STN][NSL];
+        uint4 a[STM][NSL], bre[STN][NSL];
 #pragma unroll
         for (int s = 0; s < NSL; ++s) {
 #pragma unroll
-            for (int i = 0; i < STM; ++i) {
-                const uint4 u = lp[(s * SGRP + lg) * 64 + wm * SWTM + i * 16 + lc];
-                a[i][s] = __builtin_bit_cast(h8, u);
-            }
+            for (int i = 0; i < STM; ++i) a[i][s] = lp[(s * SGRP + lg) * 64 + wm * SWTM + i * 16 + lc];
 #pragma unroll
-            for (int j = 0; j < STN; ++j) {
-                const uint4 u = lq[(s * SGRP + lg) * 64 + wn * SWTN + j * 16 + lc];
-                bre[j][s] = __builtin_bit_cast(h8, u);
-            }
+            for (int j = 0; j < STN; ++j) bre[j][s] = lq[(s * SGRP + lg) * 64 + wn * SWTN + j * 16 + lc];
         }
 #pragma unroll
         for (int t = 0; t < NSL; ++t)
 #pragma unroll
             for (int j = 0; j < STN; ++j) {
-                const h8 b = bre[j][t];
-                h8 bi;
+                const uint4 b = bre[j][t];
+                uint4 bi;
+                if constexpr (BF) {
+                    // (re, im) half pairs -> (im, -re): swap the halves of each
+                    // word, then flip the sign bit of the new high half
+                    auto im_word = [](unsigned w) { return ((w >> 16) | (w << 16)) ^ 0x80000000u; };
+                    bi = uint4{im_word(b.x), im_word(b.y), im_word(b.z), im_word(b.w)};
+                } else {
+                    const h8 bh = __builtin_bit_cast(h8, b);
+                    h8 bih;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    bi[2 * q] = b[2 * q + 1];
-                    bi[2 * q + 1] = -b[2 * q];
+                    for (int q = 0; q < 4; ++q) {
+                        bih[2 * q] = bh[2 * q + 1];
+                        bih[2 * q + 1] = -bh[2 * q];
+                    }
+                    bi = __builtin_bit_cast(uint4, bih);
                 }
 #pragma unroll
                 for (int s = 0; s + t < NLEV; ++s) {   // levels (s+1)+(t+1) <= NSL+1
                     const int c = s + t;
 #pragma unroll
                     for (int i = 0; i < STM; ++i) {
-                        lre[i][j][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[i][s], b, lre[i][j][c], 0, 0, 0);
-                        lim[i][j][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[i][s], bi, lim[i][j][c], 0, 0, 0);
+                        if constexpr (BF) {
+                            const bh8 x = __builtin_bit_cast(bh8, a[i][s]);
+                            lre[i][j][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                x, __builtin_bit_cast(bh8, b), lre[i][j][c], 0, 0, 0);
+                            lim[i][j][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                x, __builtin_bit_cast(bh8, bi), lim[i][j][c], 0, 0, 0);
+                        } else {
+                            const h8 x = __builtin_bit_cast(h8, a[i][s]);
+                            lre[i][j][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                                x, __builtin_bit_cast(h8, b), lre[i][j][c], 0, 0, 0);
+                            lim[i][j][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                                x, __builtin_bit_cast(h8, bi), lim[i][j][c], 0, 0, 0);
+                        }
                     }
                 }
             }
@@ -362,6 +397,7 @@ __device__ __forceinline__ void split_segment(const SplitSeg sg, int n_g, int gr
     }
 }
 
+template <bool BF>
 __global__ void __launch_bounds__(SNT)
 k_split_reduce(SplitArgs args) {
     __shared__ uint4 lds[2 * 2 * LDS_OP];   // 2 buffers x (P, Q)
@@ -388,13 +424,13 @@ k_split_reduce(SplitArgs args) {
 
     if (isH) {
         const SplitSeg h0 = args.h[0], h1 = args.h[1], h2 = args.h[2];
-        split_segment(h0, n_g, args.groups, m0, n0, acc, lds);
-        split_segment(h1, n_g, args.groups, m0, n0, acc, lds);
-        split_segment(h2, n_g, args.groups, m0, n0, acc, lds);
+        split_segment<BF>(h0, n_g, args.groups, m0, n0, acc, lds);
+        split_segment<BF>(h1, n_g, args.groups, m0, n0, acc, lds);
+        split_segment<BF>(h2, n_g, args.groups, m0, n0, acc, lds);
     } else {
         const SplitSeg s0 = args.s[0], s1 = args.s[1];
-        split_segment(s0, n_g, args.groups, m0, n0, acc, lds);
-        split_segment(s1, n_g, args.groups, m0, n0, acc, lds);
+        split_segment<BF>(s0, n_g, args.groups, m0, n0, acc, lds);
+        split_segment<BF>(s1, n_g, args.groups, m0, n0, acc, lds);
     }
 
     double2 *out = isH ? args.H : args.S;
@@ -429,11 +465,10 @@ k_split_reduce(SplitArgs args) {
 // most 28544 < 2^15 per real product, so a level stays exact for 2^16 real
 // products: the accumulators are combined in FP64 (Horner, scaled by
 // 2^(eP + eQ - 14)) only at the end of each (P, Q) segment and every 32768
-// complex rows, into an FP64 accumulator tile held in LDS across the
-// segments of the output (each element read-modified-written by the lane
-// that owns it, in a fixed order: deterministic); each output element is
-// stored to memory once, after its last segment. No FP64 work sits in the K
-// loop.
+// complex rows, into FP64 accumulators held in registers across the
+// segments of the output tile (a fixed order: deterministic); each output
+// element is stored to memory once, after its last segment. No FP64 work
+// sits in the K loop.
 //
 // Errors left: remainders (2^-36 of the column maxima on each side),
 // dropped pairs (s + t = 7: four pairs of |sig sig'| <= 2^12 at 2^-49, i.e.
@@ -443,8 +478,7 @@ k_split_reduce(SplitArgs args) {
 // rows (one MFMA K step of 64 int8). Operand slices go straight from global
 // memory to LDS (16-byte direct loads of 64 columns; 40 per stage) through
 // two 40 KiB LDS buffers (the next stage loads while the current one is
-// multiplied), so no staging registers are needed; with the 64 KiB
-// accumulator tile one block takes 144 KiB of the CU's 160 KiB.
+// multiplied), so no staging registers are needed.
 
 typedef int i4 __attribute__((ext_vector_type(4)));
 typedef unsigned short us2 __attribute__((ext_vector_type(2)));
@@ -526,14 +560,17 @@ __device__ __forceinline__ unsigned im_pairs(unsigned d) {
     return __builtin_bit_cast(unsigned, h);
 }
 
-// One (P, Q) segment into the tile's FP64 accumulator acc (64 x 64 complex
-// values in LDS, element (r, c) at r * 64 + c; each element is only ever
-// touched by the lane that owns it in the MFMA layout, so no barrier is
-// needed around it). first: the segment's first flush writes instead of
-// adding. The segment is taken by value for the same reason as
-// split_segment.
+// FP64 sums of a wave's outputs across the segments of its tile.
+struct Acc8 {
+    double re[T8M][T8N][4];
+    double im[T8M][T8N][4];
+};
+
+// One (P, Q) segment into the FP64 accumulators. first: the segment's first
+// flush writes instead of adding. The segment is taken by value for the
+// same reason as split_segment.
 __device__ __forceinline__ void split8_segment(const Split8Seg sg, int n_g, int groups, int m0,
-                                               int n0, bool first, double2 *acc, uint4 *bufs0,
+                                               int n0, bool first, Acc8 &acc, uint4 *bufs0,
                                                uint4 *bufs1) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -630,14 +667,13 @@ __device__ __forceinline__ void split8_segment(const Split8Seg sg, int n_g, int 
                         tr = fma(tr, 1.0 / 128.0, (double)lre[i][j][lv][v]);
                         ti = fma(ti, 1.0 / 128.0, (double)lim[i][j][lv][v]);
                     }
-                    double2 *e = acc + r * B8 + c;
-                    double2 x = double2{tr * w, ti * w};
-                    if (!write) {
-                        const double2 prev = *e;
-                        x.x += prev.x;
-                        x.y += prev.y;
+                    if (write) {
+                        acc.re[i][j][v] = tr * w;
+                        acc.im[i][j][v] = ti * w;
+                    } else {
+                        acc.re[i][j][v] += tr * w;
+                        acc.im[i][j][v] += ti * w;
                     }
-                    *e = x;
                 }
         }
         clear();
@@ -672,7 +708,6 @@ __global__ void __launch_bounds__(NT8)
 k_split8_reduce(Split8Args args) {
     __shared__ uint4 bufA[BUF8];
     __shared__ uint4 bufB[BUF8];
-    __shared__ double2 acc[B8 * B8];   // the tile's FP64 sums across segments
 
     int b = blockIdx.x;
     const bool isH = b < args.ntri8;
@@ -686,6 +721,7 @@ k_split8_reduce(Split8Args args) {
     const int n_g = args.n_g;
     const int m0 = ti * B8, n0 = tj * B8;
 
+    Acc8 acc;
     if (isH) {
         const Split8Seg h0 = args.h[0], h1 = args.h[1], h2 = args.h[2];
         split8_segment(h0, n_g, args.groups, m0, n0, true, acc, bufA, bufB);
@@ -707,9 +743,9 @@ k_split8_reduce(Split8Args args) {
         for (int i = 0; i < T8M; ++i)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int r = wm * (B8 / W8M) + i * 16 + 4 * (lane >> 4) + v;
-                const int gp = m0 + r;
-                if (gp < n_g && g <= gp) out[(long long)gp * n_g + g] = acc[r * B8 + (g - n0)];
+                const int gp = m0 + wm * (B8 / W8M) + i * 16 + 4 * (lane >> 4) + v;
+                if (gp < n_g && g <= gp)
+                    out[(long long)gp * n_g + g] = double2{acc.re[i][j][v], acc.im[i][j][v]};
             }
     }
 }
@@ -721,7 +757,7 @@ size_t split_slice_bytes(int K, int n_g) {
     return (size_t)NSL * groups * n_g * 16;
 }
 
-hipError_t launch_slice(const SliceSrc &src, int K, int n_g, hipStream_t st) {
+hipError_t launch_slice(const SliceSrc &src, int K, int n_g, hipStream_t st, bool bf16) {
     const int groups = (K + 15) / 16 * 4;
     hipLaunchKernelGGL(k_zero_u64, dim3((n_g + 255) / 256), dim3(256), 0, st, src.mx, n_g);
     hipError_t e = hipGetLastError();
@@ -730,14 +766,18 @@ hipError_t launch_slice(const SliceSrc &src, int K, int n_g, hipStream_t st) {
                        src, K, n_g);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const long long items = (long long)groups * n_g;
-    hipLaunchKernelGGL(k_slice, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, st, src, K,
-                       n_g, groups);
+    if (bf16)
+        hipLaunchKernelGGL(k_slice<true>, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, st,
+                           src, K, n_g, groups);
+    else
+        hipLaunchKernelGGL(k_slice<false>, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, st,
+                           src, K, n_g, groups);
     return hipGetLastError();
 }
 
 hipError_t launch_split_reduce(int K, int n_g, const SliceView (&hseg)[3][2],
                                const SliceView (&sseg)[2][2], double2 *H, double2 *S,
-                               hipStream_t st) {
+                               hipStream_t st, bool bf16) {
     SplitArgs a;
     for (int i = 0; i < 3; ++i)
         a.h[i] = SplitSeg{hseg[i][0].S, hseg[i][1].S, hseg[i][0].mx, hseg[i][1].mx};
@@ -750,7 +790,8 @@ hipError_t launch_split_reduce(int K, int n_g, const SliceView (&hseg)[3][2],
     a.nt = (n_g + SBM - 1) / SBM;
     a.ntri = a.nt * (a.nt + 1) / 2;
     a.ntri8 = (a.ntri + 7) / 8 * 8;
-    hipLaunchKernelGGL(k_split_reduce, dim3(2 * a.ntri8), dim3(SNT), 0, st, a);
+    if (bf16) hipLaunchKernelGGL(k_split_reduce<true>, dim3(2 * a.ntri8), dim3(SNT), 0, st, a);
+    else hipLaunchKernelGGL(k_split_reduce<false>, dim3(2 * a.ntri8), dim3(SNT), 0, st, a);
     return hipGetLastError();
 }
 

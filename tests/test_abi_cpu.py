@@ -91,7 +91,7 @@ def test_null_outputs():
 def test_build_ex_option_checks():
     lib = P.load_library()
     assert lib.hs_build_ex(*[FAKE] * 6, 2, 4, 8, FAKE, FAKE, None) == -12
-    for bad in (4, -1):
+    for bad in (5, -1):
         opt = Bd.hs_options()
         opt.mode = bad
         assert lib.hs_build_ex(*[FAKE] * 6, 2, 4, 8, FAKE, FAKE, ctypes.byref(opt)) == -12
@@ -160,7 +160,9 @@ def test_split_mode_workspace():
     assert i8 < split   # 5 bytes per real value against 8
     # the 3M form changes only the arithmetic of the reductions
     assert P.hs_workspace_bytes(10, None, 49, 1000, P.HS_FP64_3M) == fp64
-    assert P.hs_workspace_bytes(10, None, 49, 1000, 4) == 0
+    # BF16 slices take the FP16 slices' room; an unknown mode none
+    assert P.hs_workspace_bytes(10, None, 49, 1000, P.HS_SPLIT_BF16) == split
+    assert P.hs_workspace_bytes(10, None, 49, 1000, 5) == 0
     assert P.hs_workspace_bytes(10, None, 49, 1000, -1) == 0
 
 

@@ -4,7 +4,8 @@ reduction mode; complex U; the paper's two system shapes.
 * bench.py times builds whose per-atom stage is the batched persistent launch
   (batch = 1) with tile shapes the autotuner picks for the workload; here that
   exact configuration is built at N_A = 100, N_L = 81, N_G = 8000 in each of
-  the four reduction modes (FP64, split FP16, split INT8, FP64 3M) and its
+  the five reduction modes (FP64, split FP16, split INT8, FP64 3M, split
+  BF16) and its
   sampled columns and bilinear probes are compared with the oracle.
 * U enters S only through |u|^2 (Sec. 2, the U_a^H U_a factor of the equation
   for S); with complex U a kernel that squared Re(u) or u itself would
@@ -47,7 +48,7 @@ def precision():
     return p, _tuned(p)
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2, 3], ids=lambda m: MODE_NAME[m])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4], ids=lambda m: MODE_NAME[m])
 def test_bench_configuration_sampled(precision, mode):
     from paper_1611_00606_amd import DeviceBuild
     p, tuning = precision
@@ -69,7 +70,7 @@ CU_CASES = {
 
 @pytest.mark.parametrize("batch", [0, 1])
 @pytest.mark.parametrize("case", list(CU_CASES))
-@pytest.mark.parametrize("mode", [0, 1, 2, 3], ids=lambda m: MODE_NAME[m])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4], ids=lambda m: MODE_NAME[m])
 def test_complex_u_full(mode, case, batch):
     from paper_1611_00606_amd import DeviceBuild
     p = CU_CASES[case]()

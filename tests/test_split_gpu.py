@@ -1,4 +1,4 @@
-"""Split-precision forms (HS_SPLIT_F16, HS_SPLIT_I8) against the CPU oracle.
+"""Split-precision forms (HS_SPLIT_F16, HS_SPLIT_I8, HS_SPLIT_BF16) against the CPU oracle.
 
 The tolerance for this form: relative Frobenius error
 <= 1e-9 for H and for S, each stated separately. The outputs stay exactly
@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 
 TOL = 1e-9
 SPLIT = 1
-MODES = [1, 2]   # HS_SPLIT_F16, HS_SPLIT_I8
+MODES = [1, 2, 4]   # HS_SPLIT_F16, HS_SPLIT_I8, HS_SPLIT_BF16
 
 
 def _run(p, mode=SPLIT):
@@ -152,3 +152,14 @@ def test_split_in_serving_context(mode):
     torch.cuda.synchronize()
     assert np.array_equal(H.cpu().numpy(), H1) and np.array_equal(S.cpu().numpy(), S1)
     ctx.close()
+
+
+@pytest.mark.parametrize("name", ["plain_gpu_failing", "mixed_nl", "wide_range", "long_contraction"])
+def test_bf16_slices_equal_f16_slices(name):
+    """The slices are integers of at most 9 bits, exact in BF16 as in FP16,
+    and their products sum exactly in FP32 either way: the BF16 form gives
+    bitwise the FP16 form's H and S."""
+    p = CASES[name]()
+    Hf, Sf, i_f = _run(p, 1).results()
+    Hb, Sb, i_b = _run(p, 4).results()
+    assert np.array_equal(Hf, Hb) and np.array_equal(Sf, Sb) and np.array_equal(i_f, i_b)
