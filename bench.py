@@ -42,11 +42,15 @@ SPLIT_I8_PER_FP64 = 15.0
 # FP64 MFMA flops the 3M form issues per FP64 flop of the reductions: 3 real
 # products per complex multiply-add instead of 4.
 FP64_3M_PER_FP64 = 0.75
+# INT8 MFMA ops of the modular form per FP64 flop: 11 moduli x 2 MFMAs x 2
+# interleaved products x 2 ops = 88 per complex multiply-add.
+CRT_I8_PER_FP64 = 11.0
 
 
 # HBM traffic records: rocprofv3 counter summaries under profiles/, each
 # tagged with a digest of the kernel's sources (so a record of older code is
 # never reported) and the bytes one launch moved on the N_G = 8000 workload.
+SPLIT_SOURCES = ["paper_1611_00606_amd/csrc/k_split.hip", "paper_1611_00606_amd/csrc/split_common.h"]
 TRAFFIC_RECORDS = {
     "k_reduce": ("k_reduce_precision_ng8000.md",
                  ["paper_1611_00606_amd/csrc/zmfma_tile.h", "paper_1611_00606_amd/csrc/zmfma_direct.h",
@@ -54,10 +58,11 @@ TRAFFIC_RECORDS = {
     "k_reduce_3m": ("k_reduce_3m_precision_ng8000.md",
                     ["paper_1611_00606_amd/csrc/zmfma_tile.h", "paper_1611_00606_amd/csrc/zmfma_direct.h",
                      "paper_1611_00606_amd/csrc/k_reduce.hip"]),
-    "k_split_reduce": ("k_split_reduces_precision_ng8000.md", ["paper_1611_00606_amd/csrc/k_split.hip"]),
-    "k_split8_reduce": ("k_split_reduces_precision_ng8000.md", ["paper_1611_00606_amd/csrc/k_split.hip"]),
-    "k_split_reduce_bf16": ("k_split_reduces_precision_ng8000.md",
-                            ["paper_1611_00606_amd/csrc/k_split.hip"]),
+    "k_split_reduce": ("k_split_reduces_precision_ng8000.md", SPLIT_SOURCES),
+    "k_split8_reduce": ("k_split_reduces_precision_ng8000.md", SPLIT_SOURCES),
+    "k_split_reduce_bf16": ("k_split_reduces_precision_ng8000.md", SPLIT_SOURCES),
+    "k_crt_reduce": ("k_crt_reduce_precision_ng8000.md",
+                     ["paper_1611_00606_amd/csrc/k_crt.hip", "paper_1611_00606_amd/csrc/split_common.h"]),
 }
 TRAFFIC_UNIT = ("HBM bytes per launch: rocprofv3 TCC_EA0 read requests by size (32, 64, 128 B) "
                 "and write requests by size (32, 64 B), one launch on this workload")
@@ -279,6 +284,14 @@ SPLIT_MODES = {
             per_fp64=SPLIT_F16_PER_FP64, peak=FP16_MFMA_PEAK_TFLOPS,
             unit="TFLOP/s (BF16 MFMA flops issued)",
             kernel="slicing + split reduction (phase 2..3)", phase="slice_and_reduce_HS"),
+    5: dict(name="split_i8_crt", traffic_kernel="k_crt_reduce", slice_bytes=22.0,
+            mode="split_i8_crt (36-bit integers per operand column, exact products modulo 11 "
+                 "coprime moduli <= 255 on INT8 MFMA, Chinese-remainder reconstruction, FP64 "
+                 "scaling per segment)",
+            per_fp64=CRT_I8_PER_FP64, peak=INT8_MFMA_PEAK_TOPS,
+            unit="TOP/s (INT8 MFMA ops issued)",
+            kernel="residues + modular reduction + reconstruction (phase 2..3)",
+            phase="slice_and_reduce_HS"),
     3: dict(name="fp64_3m", traffic_kernel="k_reduce_3m", slice_bytes=16.0,
             mode="fp64_3m (complex FP64 with 3 real MFMA products per complex product: "
                  "T1 = pr qr, T2 = pi qi, T3 = (pr - pi)(qr + qi); Re = T1 + T2, Im = T3 - T1 + T2)",
@@ -313,7 +326,11 @@ def split_bench(p, steps: int, warmup: int, fp64_ms: float, hip, mode: int, n_co
     issued = m["per_fp64"] * reduction_flops(p.nl, p.N_G) / (ph[2] * 1e-3) / 1e12
     # split forms read six sliced operands (16 B per complex element for the
     # FP16 slices, 10 B for the INT8 ones); the 3M form the four FP64 ones
-    alg_bytes = reduction_bytes(p.K, p.N_G, m["slice_bytes"], 6 if mode in (1, 2, 4) else 4)
+    alg_bytes = reduction_bytes(p.K, p.N_G, m["slice_bytes"], 6 if mode in (1, 2, 4, 5) else 4)
+    if mode == 5:
+        # the modular reduction writes each segment's residues (5 segments x
+        # 11 moduli x 2 bytes per lower-triangle element) instead of H and S
+        alg_bytes += (55.0 - 16.0) * float(p.N_G) ** 2
     traffic = measured_traffic(p.name, m["traffic_kernel"])
     return {
         "mode": m["mode"],
@@ -721,9 +738,10 @@ def main():
                     help="skip the serving-form measurement (k-point builds/s, p50/p99)")
     ap.add_argument("--no-split", action="store_true",
                     help="skip the split-precision and 3M measurements")
-    ap.add_argument("--split-modes", default="1,2,3,4",
+    ap.add_argument("--split-modes", default="1,2,3,4,5",
                     help="alternative reduction modes to measure (1 = HS_SPLIT_F16, "
-                         "2 = HS_SPLIT_I8, 3 = HS_FP64_3M, 4 = HS_SPLIT_BF16)")
+                         "2 = HS_SPLIT_I8, 3 = HS_FP64_3M, 4 = HS_SPLIT_BF16, "
+                         "5 = HS_SPLIT_I8_CRT)")
     ap.add_argument("--per-atom", choices=["batched", "separate"], default="batched",
                     help="per-atom stage of the timed builds: the batched persistent launch with "
                          "autotuned tile shapes, or separate preparation and product launches")

@@ -114,13 +114,27 @@ enum {
  *                 (magnitude <= 256), exact in BF16 too, and their products
  *                 accumulate exactly in FP32 either way, so H and S are
  *                 bitwise those of HS_SPLIT_F16 (MI355X runs BF16 and FP16
- *                 MFMA at the same dense rate). Workspace as HS_SPLIT_F16. */
+ *                 MFMA at the same dense rate). Workspace as HS_SPLIT_F16.
+ *   HS_SPLIT_I8_CRT modular form on INT8 MFMA: each operand column is scaled by
+ *                 a power of two and rounded to signed integers of b bits
+ *                 (b = 36 for contraction lengths up to about 5e4, one bit
+ *                 less per factor of four beyond); the exact integer products
+ *                 of each contraction segment are formed modulo 11 pairwise
+ *                 coprime moduli <= 255 (symmetric residues in int8, INT32
+ *                 sums, one INT8 MFMA product per modulus instead of the 15
+ *                 slice pairs of HS_SPLIT_I8) and rebuilt by the Chinese
+ *                 remainder theorem (mixed-radix digits) before the binary64
+ *                 scaling. The only error is the rounding of the operands,
+ *                 2^-36 of their column maxima per element. Workspace: 22
+ *                 bytes per operand element and a residue buffer of about
+ *                 55 N_G^2 bytes. Inputs must be finite. */
 typedef enum {
     HS_FP64 = 0,
     HS_SPLIT_F16 = 1,
     HS_SPLIT_I8 = 2,
     HS_FP64_3M = 3,
-    HS_SPLIT_BF16 = 4
+    HS_SPLIT_BF16 = 4,
+    HS_SPLIT_I8_CRT = 5
 } hs_mode;
 
 /* Tile shapes of the batched per-atom stage (see hs_options.batch): shape id

@@ -17,6 +17,7 @@ from ._binding import (  # noqa: F401
     HS_SPLIT_I8,
     HS_FP64_3M,
     HS_SPLIT_BF16,
+    HS_SPLIT_I8_CRT,
     HS_MAX_NL,
     HS_NUM_PHASE_EVENTS,
     HS_NUM_TILE_CONFIGS,

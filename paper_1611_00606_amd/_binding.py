@@ -28,6 +28,7 @@ HS_SPLIT_F16 = 1
 HS_SPLIT_I8 = 2
 HS_FP64_3M = 3
 HS_SPLIT_BF16 = 4
+HS_SPLIT_I8_CRT = 5
 HS_MAX_NL = 128
 HS_NUM_PHASE_EVENTS = 5
 HS_NUM_TILE_CONFIGS = 6

@@ -139,6 +139,7 @@ size_t AtomPlan::kpoint_bytes(int n_g, int mode) const {
     size_t b = 2 * align_up(16 * (size_t)K * (size_t)n_g) + BatchBufs::bytes(n_atoms);
     if (split_mode(mode))
         b += NSPLIT * (align_up(slice_bytes(mode, K, n_g)) + align_up(8 * (size_t)n_g));
+    if (mode == HS_SPLIT_I8_CRT) b += align_up(crt_work_bytes(n_g));
     return b;
 }
 
@@ -199,6 +200,7 @@ void KpointBufs::carve(const AtomPlan &p, int n_g, int mode, char *base) {
         mx[i] = reinterpret_cast<unsigned long long *>(base + o);
         o += align_up(8 * (size_t)n_g);
     }
+    crt = mode == HS_SPLIT_I8_CRT ? base + o : nullptr;
 }
 
 hipError_t enqueue_atoms(const AtomPlan &p, const AtomBufs &ab, const double2 *T_AA,
@@ -255,17 +257,21 @@ hipError_t enqueue_kpoint(const AtomPlan &p, const AtomBufs &ab, int n_g, int mo
             {kb.W, nullptr, nullptr, nullptr, kb.mx[5], kb.sl[5]},
         };
         for (int i = 0; i < NSPLIT; ++i) {
-            e = mode == HS_SPLIT_I8 ? launch_slice8(src[i], K, n_g, st)
-                                    : launch_slice(src[i], K, n_g, st, mode == HS_SPLIT_BF16);
+            if (mode == HS_SPLIT_I8_CRT) e = launch_residue(src[i], K, n_g, st);
+            else if (mode == HS_SPLIT_I8) e = launch_slice8(src[i], K, n_g, st);
+            else e = launch_slice(src[i], K, n_g, st, mode == HS_SPLIT_BF16);
             if (e != hipSuccess) return e;
         }
         SliceView v[NSPLIT];
         for (int i = 0; i < NSPLIT; ++i) v[i] = SliceView{kb.sl[i], kb.mx[i]};
         const SliceView hseg[3][2] = {{v[2], v[3]}, {v[3], v[2]}, {v[4], v[5]}};
         const SliceView sseg[2][2] = {{v[0], v[0]}, {v[1], v[1]}};
-        e = mode == HS_SPLIT_I8 ? launch_split8_reduce(K, n_g, hseg, sseg, H, S, st)
-                                : launch_split_reduce(K, n_g, hseg, sseg, H, S, st,
-                                                      mode == HS_SPLIT_BF16);
+        if (mode == HS_SPLIT_I8_CRT)
+            e = launch_crt_reduce(K, n_g, hseg, sseg, kb.crt, H, S, st);
+        else if (mode == HS_SPLIT_I8)
+            e = launch_split8_reduce(K, n_g, hseg, sseg, H, S, st);
+        else
+            e = launch_split_reduce(K, n_g, hseg, sseg, H, S, st, mode == HS_SPLIT_BF16);
     } else {
         e = launch_reduce(p.K, n_g, A, B, kb.Z, kb.W, ab.sel, ab.d, H, S, st,
                           mode == HS_FP64_3M);

@@ -68,12 +68,13 @@ const char *message_for(int status);   // the last message if it explains `statu
 int hip_fail(hipError_t e, const char *where);   // records the message, returns HS_ERR_HIP
 int check_device();                              // HS_OK on gfx950, else an error status
 int num_cus();                                   // compute units of the current device
-inline bool valid_mode(int mode) {   // HS_FP64, HS_SPLIT_F16, HS_SPLIT_I8, HS_FP64_3M, HS_SPLIT_BF16
+inline bool valid_mode(int mode) {   // HS_FP64 .. HS_SPLIT_I8_CRT
     return mode == HS_FP64 || mode == HS_SPLIT_F16 || mode == HS_SPLIT_I8 || mode == HS_FP64_3M ||
-           mode == HS_SPLIT_BF16;
+           mode == HS_SPLIT_BF16 || mode == HS_SPLIT_I8_CRT;
 }
-inline bool split_mode(int mode) {
-    return mode == HS_SPLIT_F16 || mode == HS_SPLIT_I8 || mode == HS_SPLIT_BF16;
+inline bool split_mode(int mode) {   // the operands are sliced (or cut into residues)
+    return mode == HS_SPLIT_F16 || mode == HS_SPLIT_I8 || mode == HS_SPLIT_BF16 ||
+           mode == HS_SPLIT_I8_CRT;
 }
 
 // Split-precision reductions (k_split.hip). A sliced operand: rows of X (or
@@ -93,6 +94,8 @@ struct SliceView {
     const unsigned long long *mx;
 };
 size_t split_slice_bytes(int K, int n_g);
+// zero mx, then the column maxima of src into it
+hipError_t launch_colmax(const SliceSrc &src, int K, int n_g, hipStream_t st);
 // bf16: the same slices held as BF16 and multiplied on BF16 MFMA
 hipError_t launch_slice(const SliceSrc &src, int K, int n_g, hipStream_t st, bool bf16);
 // H segments (Z,B), (B,Z), (P3,W); S segments (A,A), (Bs,Bs): [segment][P or Q]
@@ -106,7 +109,19 @@ hipError_t launch_slice8(const SliceSrc &src, int K, int n_g, hipStream_t st);
 hipError_t launch_split8_reduce(int K, int n_g, const SliceView (&hseg)[3][2],
                                 const SliceView (&sseg)[2][2], double2 *H, double2 *S,
                                 hipStream_t st);
+// Modular INT8 form (k_crt.hip): residues R [NMOD][groups][N_G][16 int8],
+// groups = 16 * ceil(K / 128), of each operand's b-bit integers; the
+// reduction writes each segment's residues into `work` (crt_work_bytes) and
+// rebuilds H and S from them.
+size_t crt_residue_bytes(int K, int n_g);
+size_t crt_work_bytes(int n_g);
+int crt_bits(int K);   // integer width b of the operands for contraction length K
+hipError_t launch_residue(const SliceSrc &src, int K, int n_g, hipStream_t st);
+hipError_t launch_crt_reduce(int K, int n_g, const SliceView (&hseg)[3][2],
+                             const SliceView (&sseg)[2][2], void *work, double2 *H, double2 *S,
+                             hipStream_t st);
 inline size_t slice_bytes(int mode, int K, int n_g) {
+    if (mode == HS_SPLIT_I8_CRT) return crt_residue_bytes(K, n_g);
     return mode == HS_SPLIT_I8 ? split8_slice_bytes(K, n_g) : split_slice_bytes(K, n_g);
 }
 // upper := conj(lower), Im(diag) := 0 for both outputs (launch_mirror1: one matrix)
@@ -196,6 +211,7 @@ struct KpointBufs {
     double2 *Z, *W;   // [K][N_G] each
     _Float16 *sl[NSPLIT];
     unsigned long long *mx[NSPLIT];
+    void *crt;        // segment residues of the modular form (else NULL)
     BatchBufs batch;
     void carve(const AtomPlan &p, int n_g, int mode, char *base);
 };

@@ -40,6 +40,7 @@
 // product (entries a few standard deviations below their column maximum)
 // about 2^-32.
 #include "hs_internal.h"
+#include "split_common.h"
 #include "zmfma_tile.h"
 
 namespace hs {
@@ -70,18 +71,6 @@ __global__ void __launch_bounds__(256) k_zero_u64(unsigned long long *p, int n) 
     if (i < n) p[i] = 0ull;
 }
 
-__device__ __forceinline__ double2 slice_src_row(const SliceSrc &src, int k, int n_g, int n) {
-    const double2 *row = src.X;
-    if (src.sel && src.sel[k]) row = src.Xalt;
-    double2 v = row[(long long)k * n_g + n];
-    if (src.rscale) {
-        const double w = sqrt(src.rscale[k]);
-        v.x *= w;
-        v.y *= w;
-    }
-    return v;
-}
-
 __global__ void __launch_bounds__(256)
 k_colmax(SliceSrc src, int K, int n_g) {
     __shared__ double red[4][64];
@@ -103,14 +92,6 @@ k_colmax(SliceSrc src, int K, int n_g) {
         m = fmax(fmax(red[0][c], red[1][c]), fmax(red[2][c], red[3][c]));
         atomicMax(src.mx + n, (unsigned long long)__double_as_longlong(m));
     }
-}
-
-// exponent e with column max < 2^e (0 for an all-zero column)
-__device__ __forceinline__ int col_exp(const unsigned long long *mx, int n) {
-    const double m = __longlong_as_double((long long)mx[n]);
-    int e = 0;
-    if (m > 0.0) frexp(m, &e);
-    return e;
 }
 
 // ---------------------------------------------------------------------------
@@ -203,35 +184,6 @@ struct SplitArgs {
     int n_g, groups;         // groups = K padded to 16, over 4
     int nt, ntri, ntri8;
 };
-
-__device__ __forceinline__ void sband_tile(int t, int nt, int &ti, int &tj, int band = SBAND) {
-    int c0 = 0;
-    for (;;) {
-        const int m = nt - c0;
-        if (m <= 0) {
-            ti = tj = -1;
-            return;
-        }
-        const int w = m < band ? m : band;
-        const int tri = w * (w + 1) / 2;
-        const int cnt = tri + (m - w) * w;
-        if (t < cnt) {
-            if (t < tri) {
-                int r = 0;
-                while ((r + 1) * (r + 2) / 2 <= t) ++r;
-                ti = c0 + r;
-                tj = c0 + (t - r * (r + 1) / 2);
-            } else {
-                const int u = t - tri;
-                ti = c0 + w + u / w;
-                tj = c0 + u % w;
-            }
-            return;
-        }
-        t -= cnt;
-        c0 += band;
-    }
-}
 
 struct Acc64 {
     double re[STM][STN][4];
@@ -409,7 +361,7 @@ k_split_reduce(SplitArgs args) {
     const int t = (b % 8) * per_xcd + b / 8;
     if (t >= args.ntri) return;
     int ti, tj;
-    sband_tile(t, args.nt, ti, tj);
+    sband_tile(t, args.nt, ti, tj, SBAND);
     if (ti < 0) return;
     const int m0 = ti * SBM, n0 = tj * SBN;
     const int n_g = args.n_g;
@@ -481,7 +433,6 @@ k_split_reduce(SplitArgs args) {
 // multiplied), so no staging registers are needed.
 
 typedef int i4 __attribute__((ext_vector_type(4)));
-typedef unsigned short us2 __attribute__((ext_vector_type(2)));
 
 constexpr int NSL8 = 5;                  // slices per value
 constexpr int NLEV8 = 5;                 // levels c = 2 .. 6
@@ -551,14 +502,6 @@ struct Split8Args {
     int n_g, groups;          // groups of 8 complex rows, a multiple of GRP8
     int nt, ntri, ntri8;
 };
-
-// (Re, Im) byte pairs -> (Im, -Re): conj(p) q's imaginary part as a dot product.
-__device__ __forceinline__ unsigned im_pairs(unsigned d) {
-    const unsigned t = __builtin_amdgcn_perm(d, d, 0x02030001u) ^ 0xff00ff00u;
-    us2 h = __builtin_bit_cast(us2, t);
-    h += us2{0x0100, 0x0100};   // per 16-bit half: high byte ~b + 1 = -b, no carry across
-    return __builtin_bit_cast(unsigned, h);
-}
 
 // FP64 sums of a wave's outputs across the segments of its tile.
 struct Acc8 {
@@ -757,14 +700,19 @@ size_t split_slice_bytes(int K, int n_g) {
     return (size_t)NSL * groups * n_g * 16;
 }
 
-hipError_t launch_slice(const SliceSrc &src, int K, int n_g, hipStream_t st, bool bf16) {
-    const int groups = (K + 15) / 16 * 4;
+hipError_t launch_colmax(const SliceSrc &src, int K, int n_g, hipStream_t st) {
     hipLaunchKernelGGL(k_zero_u64, dim3((n_g + 255) / 256), dim3(256), 0, st, src.mx, n_g);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_colmax, dim3((n_g + 63) / 64, (K + CROWS - 1) / CROWS), dim3(256), 0, st,
                        src, K, n_g);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_slice(const SliceSrc &src, int K, int n_g, hipStream_t st, bool bf16) {
+    const int groups = (K + 15) / 16 * 4;
+    hipError_t e = launch_colmax(src, K, n_g, st);
+    if (e != hipSuccess) return e;
     const long long items = (long long)groups * n_g;
     if (bf16)
         hipLaunchKernelGGL(k_slice<true>, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, st,
@@ -802,12 +750,8 @@ size_t split8_slice_bytes(int K, int n_g) {
 
 hipError_t launch_slice8(const SliceSrc &src, int K, int n_g, hipStream_t st) {
     const int groups = (K + 31) / 32 * GRP8;
-    hipLaunchKernelGGL(k_zero_u64, dim3((n_g + 255) / 256), dim3(256), 0, st, src.mx, n_g);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_colmax(src, K, n_g, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_colmax, dim3((n_g + 63) / 64, (K + CROWS - 1) / CROWS), dim3(256), 0, st,
-                       src, K, n_g);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     const long long items = (long long)groups * n_g;
     hipLaunchKernelGGL(k_slice8, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, st, src, K,
                        n_g, groups);

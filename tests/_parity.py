@@ -16,8 +16,9 @@ from hs_inputs import cn
 # and the split-precision forms.
 TOL_FP64 = 1e-12
 TOL_SPLIT = 1e-9
-MODE_TOL = {0: TOL_FP64, 1: TOL_SPLIT, 2: TOL_SPLIT, 3: TOL_FP64, 4: TOL_SPLIT}
-MODE_NAME = {0: "fp64", 1: "split_f16", 2: "split_i8", 3: "fp64_3m", 4: "split_bf16"}
+MODE_TOL = {0: TOL_FP64, 1: TOL_SPLIT, 2: TOL_SPLIT, 3: TOL_FP64, 4: TOL_SPLIT, 5: TOL_SPLIT}
+MODE_NAME = {0: "fp64", 1: "split_f16", 2: "split_i8", 3: "fp64_3m", 4: "split_bf16",
+             5: "split_i8_crt"}
 
 
 def rel(x, y):

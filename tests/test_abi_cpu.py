@@ -91,7 +91,7 @@ def test_null_outputs():
 def test_build_ex_option_checks():
     lib = P.load_library()
     assert lib.hs_build_ex(*[FAKE] * 6, 2, 4, 8, FAKE, FAKE, None) == -12
-    for bad in (5, -1):
+    for bad in (6, -1):
         opt = Bd.hs_options()
         opt.mode = bad
         assert lib.hs_build_ex(*[FAKE] * 6, 2, 4, 8, FAKE, FAKE, ctypes.byref(opt)) == -12
@@ -162,7 +162,16 @@ def test_split_mode_workspace():
     assert P.hs_workspace_bytes(10, None, 49, 1000, P.HS_FP64_3M) == fp64
     # BF16 slices take the FP16 slices' room; an unknown mode none
     assert P.hs_workspace_bytes(10, None, 49, 1000, P.HS_SPLIT_BF16) == split
-    assert P.hs_workspace_bytes(10, None, 49, 1000, 5) == 0
+    # modular form: 11 residues of 2 bytes per complex element and operand
+    # (contraction padded to 128 rows), plus the segments' residues of the
+    # 128 x 128 lower-triangle tiles (5 segments x 11 moduli x 2 bytes)
+    crt = P.hs_workspace_bytes(10, None, 49, 1000, P.HS_SPLIT_I8_CRT)
+    groups_c = (K + 127) // 128 * 16
+    nt = (1000 + 127) // 128
+    crt_res = 5 * 11 * (nt * (nt + 1) // 2) * 128 * 128 * 2
+    assert crt >= fp64 + 6 * 11 * groups_c * 1000 * 16 + crt_res
+    assert crt < fp64 + 6 * 11 * groups_c * 1000 * 16 + crt_res + 6 * (1000 * 8 + 4096) + 8192
+    assert P.hs_workspace_bytes(10, None, 49, 1000, 6) == 0
     assert P.hs_workspace_bytes(10, None, 49, 1000, -1) == 0
 
 
@@ -230,7 +239,7 @@ def test_gep_argument_checks():
         a[pos] = bad
         assert lib.hs_gep_reduce(*a) == -(pos + 1)
         assert lib.hs_gep_reduce_ex(*a, P.HS_FP64_3M) == -(pos + 1)
-    for bad_mode in (P.HS_SPLIT_F16, P.HS_SPLIT_I8, 4, -1):
+    for bad_mode in (P.HS_SPLIT_F16, P.HS_SPLIT_I8, P.HS_SPLIT_BF16, P.HS_SPLIT_I8_CRT, -1):
         assert lib.hs_gep_reduce_ex(*args, bad_mode) == -10
 
 

@@ -48,7 +48,7 @@ def precision():
     return p, _tuned(p)
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4], ids=lambda m: MODE_NAME[m])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4, 5], ids=lambda m: MODE_NAME[m])
 def test_bench_configuration_sampled(precision, mode):
     from paper_1611_00606_amd import DeviceBuild
     p, tuning = precision
@@ -70,7 +70,7 @@ CU_CASES = {
 
 @pytest.mark.parametrize("batch", [0, 1])
 @pytest.mark.parametrize("case", list(CU_CASES))
-@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4], ids=lambda m: MODE_NAME[m])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4, 5], ids=lambda m: MODE_NAME[m])
 def test_complex_u_full(mode, case, batch):
     from paper_1611_00606_amd import DeviceBuild
     p = CU_CASES[case]()

@@ -203,7 +203,7 @@ def _serve_mode(ctx, reqs, arrivals, n_slots, arena, mode, on_host):
     return recs, peak
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4], ids=lambda m: MODE_NAME[m])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4, 5], ids=lambda m: MODE_NAME[m])
 def test_serving_workload_alone_equals_mix_and_oracle(c5_atoms, c5_ctx, c5_requests, mode):
     """Each request alone (one slot, nothing else in flight): sampled columns
     and bilinear probes against the oracle. Then all eight arrive at once on
@@ -241,7 +241,7 @@ def test_serving_workload_alone_equals_mix_and_oracle(c5_atoms, c5_ctx, c5_reque
     assert all(same[i] for i in range(len(reqs))), same
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4], ids=lambda m: MODE_NAME[m])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4, 5], ids=lambda m: MODE_NAME[m])
 def test_context_complex_u_matches_oracle(mode):
     """The resident context keeps |u|^2 of a complex U (its S matches the oracle)."""
     from paper_1611_00606_amd.serving import Context

@@ -1,4 +1,5 @@
-"""Split-precision forms (HS_SPLIT_F16, HS_SPLIT_I8, HS_SPLIT_BF16) against the CPU oracle.
+"""Split-precision forms (HS_SPLIT_F16, HS_SPLIT_I8, HS_SPLIT_BF16) and the modular
+INT8 form (HS_SPLIT_I8_CRT) against the CPU oracle.
 
 The tolerance for this form: relative Frobenius error
 <= 1e-9 for H and for S, each stated separately. The outputs stay exactly
@@ -16,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 TOL = 1e-9
 SPLIT = 1
-MODES = [1, 2, 4]   # HS_SPLIT_F16, HS_SPLIT_I8, HS_SPLIT_BF16
+MODES = [1, 2, 4, 5]   # HS_SPLIT_F16, HS_SPLIT_I8, HS_SPLIT_BF16, HS_SPLIT_I8_CRT
 
 
 def _run(p, mode=SPLIT):
@@ -83,6 +84,9 @@ CASES = {
     # K = 33280 > 32768 rows: the INT8 levels are folded into the output
     # mid-segment (every 32768 rows) as well as at segment ends
     "long_contraction": lambda: make_problem(260, 128, 97, seed=10, fail_atoms=[5, 200]),
+    # K = 67840 > 65536 rows: the modular form reduces its INT32 sums
+    # mid-segment, and its integer width drops to b = 35
+    "longer_contraction": lambda: make_problem(530, 128, 65, seed=11, fail_atoms=[7]),
 }
 
 

@@ -158,3 +158,155 @@ def test_truncated_products_within_bound():
         # relative to |conj(p).q| ~ sqrt(n); the Frobenius bound the GPU
         # tests use is 1e-9
         assert np.median(errs) < 1e-9, (form, np.median(errs))
+
+
+# ---------------------------------------------------------------------------
+# Modular (CRT) INT8 form: each operand column is rounded to a signed b-bit
+# integer at its column scale; the exact integer products are computed modulo
+# eleven pairwise coprime moduli <= 255 on INT8 MFMA (symmetric residues, so
+# every residue and its negation fit int8) and rebuilt by mixed-radix
+# (Garner) reconstruction. Model written from the definitions (Chinese
+# remainder theorem, Garner's algorithm), not shared with the HIP code.
+
+CRT_MODULI = [255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 217]
+CRT_BMAX = 36
+
+
+def crt_product():
+    M = 1
+    for m in CRT_MODULI:
+        M *= m
+    return M
+
+
+def crt_bits(K):
+    """Largest b (<= CRT_BMAX) with 2 K (2^(b-1))^2 <= (M - 1) / 2: every
+    real or imaginary part of a K-row product of b-bit integers is then
+    inside the symmetric residue range of M."""
+    M = crt_product()
+    b = CRT_BMAX
+    while 2 * K * (1 << (2 * (b - 1))) > (M - 1) // 2:
+        b -= 1
+    return b
+
+
+def sym_mod(x, m):
+    r = x % m
+    return np.where(r > m // 2, r - m, r) if isinstance(r, np.ndarray) else (r - m if r > m // 2 else r)
+
+
+def crt_integers(X, b):
+    """Column scale 2^-e (max < 2^e) and rint(x 2^(b-1)) of the scaled parts."""
+    mx = np.max(np.maximum(np.abs(X.real), np.abs(X.imag)), axis=0)
+    e = np.where(mx > 0, np.frexp(mx)[1], 0)
+    sc = np.ldexp(1.0, b - 1 - e)
+    return np.rint(X.real * sc).astype(np.int64), np.rint(X.imag * sc).astype(np.int64), e
+
+
+def garner(res):
+    """Symmetric residues r_i (lists per modulus) -> the integer in
+    (-(M-1)/2, (M-1)/2) with those residues, by mixed radix digits."""
+    v = []
+    for i, m in enumerate(CRT_MODULI):
+        t = int(res[i])
+        for j in range(i):
+            t = sym_mod((t - v[j]) * pow(CRT_MODULI[j], -1, m), m)
+        v.append(sym_mod(t, m))
+    x, w = 0, 1
+    for i, m in enumerate(CRT_MODULI):
+        x += v[i] * w
+        w *= m
+    return x, v
+
+
+def test_crt_moduli_coprime_and_bit_budget():
+    from math import gcd
+    for i, a in enumerate(CRT_MODULI):
+        assert a % 2 == 1 and a <= 255
+        for c in CRT_MODULI[:i]:
+            assert gcd(a, c) == 1
+    M = crt_product()
+    assert 86 < np.log2(float(M)) < 87
+    assert crt_bits(8100) == 36 and crt_bits(25088) == 36
+    assert crt_bits(1 << 17) == 34
+    # symmetric residues of any modulus fit int8 with their negation
+    assert max((m - 1) // 2 for m in CRT_MODULI) == 127
+    # INT32 accumulation of residue products stays exact over the fold
+    # interval of the kernel (65536 complex rows = 2^17 real products)
+    assert (1 << 17) * 127 * 127 + 127 < 2 ** 31
+
+
+def test_crt_reconstruction_exact():
+    rng = np.random.default_rng(5)
+    M = crt_product()
+    half = (M - 1) // 2
+    cases = [0, 1, -1, half, -half, half - 12345, -(half - 999)]
+    cases += [int(x) for x in rng.integers(-2 ** 62, 2 ** 62, 50)]
+    cases += [int(rng.integers(-2 ** 40, 2 ** 40)) * int(rng.integers(1, 2 ** 45)) for _ in range(50)]
+    for x in cases:
+        res = [sym_mod(x, m) for m in CRT_MODULI]
+        assert all(abs(r) <= 127 for r in res)
+        y, v = garner(res)
+        assert y == x
+        assert all(abs(d) <= (m - 1) // 2 for d, m in zip(v, CRT_MODULI))
+
+
+def test_crt_garner_digits_in_float32():
+    # the kernel's digit step t = (t - v_j) c mod m_i in FP32: operands below
+    # 2^24 and the quotient never within rounding of a half-integer
+    worst = 0
+    for i, mi in enumerate(CRT_MODULI):
+        for j in range(i):
+            c = pow(CRT_MODULI[j], -1, mi)
+            c = c - mi if c > mi // 2 else c
+            for t in range(-(mi - 1) // 2, (mi - 1) // 2 + 1, 7):
+                for vj in (-(CRT_MODULI[j] - 1) // 2, 0, (CRT_MODULI[j] - 1) // 2):
+                    x = (t - vj) * c
+                    worst = max(worst, abs(x))
+                    q = np.rint(np.float32(x) * np.float32(1.0 / mi))
+                    r = np.float32(x) - np.float32(mi) * q
+                    assert r == sym_mod(x, mi)
+    assert worst < 2 ** 24
+
+
+def _crt_dot_columns(P, Q, b):
+    """conj(P)^T Q through the modular form, exactly as the kernels define it."""
+    Pr, Pi, eP = crt_integers(P, b)
+    Qr, Qi, eQ = crt_integers(Q, b)
+    n, k = P.shape[1], Q.shape[1]
+    out = np.zeros((n, k), complex)
+    for g in range(n):
+        for h in range(k):
+            re_res, im_res = [], []
+            for m in CRT_MODULI:
+                pr, pi = sym_mod(Pr[:, g], m), sym_mod(Pi[:, g], m)
+                qr, qi = sym_mod(Qr[:, h], m), sym_mod(Qi[:, h], m)
+                # INT32 sums of residue products, then reduced
+                re_res.append(sym_mod(int(np.dot(pr, qr) + np.dot(pi, qi)), m))
+                im_res.append(sym_mod(int(np.dot(pr, qi) - np.dot(pi, qr)), m))
+            xr, _ = garner(re_res)
+            xi, _ = garner(im_res)
+            # exact integer products (Python integers: they exceed int64)
+            pr_, pi_ = Pr[:, g].astype(object), Pi[:, g].astype(object)
+            qr_, qi_ = Qr[:, h].astype(object), Qi[:, h].astype(object)
+            exact_r = int(np.dot(pr_, qr_) + np.dot(pi_, qi_))
+            exact_i = int(np.dot(pr_, qi_) - np.dot(pi_, qr_))
+            assert (xr, xi) == (exact_r, exact_i)
+            w = np.ldexp(1.0, int(eP[g] + eQ[h]) - 2 * (b - 1))
+            out[g, h] = complex(float(xr) * w, float(xi) * w)
+    return out
+
+
+def test_crt_products_exact_and_within_bound():
+    rng = np.random.default_rng(6)
+    K = 3000
+    b = crt_bits(K)
+    P = (rng.standard_normal((K, 3)) + 1j * rng.standard_normal((K, 3))) * np.array([1.0, 1e-3, 1e5])
+    Q = (rng.standard_normal((K, 2)) + 1j * rng.standard_normal((K, 2))) * np.array([3.0, 1e-7])
+    P[5, 0] = 2.0 ** 3          # a column maximum that is a power of two
+    got = _crt_dot_columns(P, Q, b)
+    ref = P.conj().T @ Q
+    err = np.abs(got - ref) / (np.linalg.norm(P, axis=0)[:, None] * np.linalg.norm(Q, axis=0)[None, :])
+    # rounding both operands to b bits of their column maxima: far inside
+    # the 1e-9 bound of the split forms
+    assert np.max(err) < 2.0 ** -(b - 4)

@@ -36,7 +36,7 @@ def _static(r, **kw):
 
 
 @pytest.mark.parametrize("batch", [0, 1])
-@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4], ids=lambda m: MODE_NAME[m])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4, 5], ids=lambda m: MODE_NAME[m])
 def test_static_equals_workspace_build(mode, batch):
     from paper_1611_00606_amd import DeviceBuild
     torch = _torch()
