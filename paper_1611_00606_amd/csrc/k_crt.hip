@@ -62,6 +62,7 @@ constexpr int inv_mod_c(long long a, int m) {
 struct GarnerTab {
     int w[NMOD][NMOD];
     int u[NMOD];
+    int wu[NMOD][NMOD];   // w[i][j] u[i] mod m_i, symmetric
 };
 constexpr GarnerTab make_garner() {
     GarnerTab t{};
@@ -72,12 +73,16 @@ constexpr GarnerTab make_garner() {
             wm = wm * CRT_MOD[j] % CRT_MOD[i];
         }
         t.u[i] = sym_mod_c(inv_mod_c(wm, CRT_MOD[i]), CRT_MOD[i]);
+        for (int j = 0; j < i; ++j) t.wu[i][j] = sym_mod_c((long long)t.w[i][j] * t.u[i], CRT_MOD[i]);
     }
     return t;
 }
 constexpr GarnerTab GT = make_garner();
 static_assert(GT.u[0] == 1 && ((long long)GT.u[1] * 255 % 253 + 253) % 253 == 1, "Garner table");
-static_assert(NMOD * 127 * 127 + 127 < (1 << 24), "Garner sums exact in FP32");
+// a digit's sum r_i u_i - sum_{j<i} wu[i][j] v_j is an integer below 2^24
+static_assert(NMOD * 127 * 127 < (1 << 24), "Garner sums exact in FP32");
+// three symmetric digits fold into an integer below 2^24 (exact in FP32)
+static_assert(255LL * 253 * 251 / 2 < (1 << 24), "digit groups exact in FP32");
 
 __device__ __forceinline__ int crt_modulus(int mi) {
     int m = CRT_MOD[0];
@@ -150,7 +155,7 @@ constexpr int CITEMS = 4 * CKS;            // items per column and stage
 constexpr int COP = CITEMS * CB;           // items per operand and stage
 constexpr int CBUF = 2 * COP;
 constexpr int CFOLD = 1024;                // stages between reductions of the sums
-constexpr int CBAND = 4;
+constexpr int CBAND = 8;
 constexpr int CFRAG = CWM * CWN * CTM * CTN;   // 16 x 16 blocks per tile (64)
 constexpr int CWAVES_EU = 2;               // waves per SIMD (at most 256 registers each)
 constexpr int CNBUF = 2;                   // LDS stage buffers: CNBUF - 1 stages in flight
@@ -304,7 +309,7 @@ k_crt_reduce(CrtArgs args) {
     fold();
 
     // residues of the 4 rows (4 lg + v) of column lc of every 16 x 16 block:
-    // Re in x, Im in y, one byte per row
+    // Re in x, Im in y, one byte per row, stored as r + 127 (0 .. 254)
     uint2 *out = args.out + ((long long)job * args.ntri + t) * CFRAG * 64;
 #pragma unroll
     for (int i = 0; i < CTM; ++i)
@@ -313,8 +318,8 @@ k_crt_reduce(CrtArgs args) {
             unsigned re = 0u, im = 0u;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                re |= ((unsigned)accr[i][j][v] & 0xffu) << (8 * v);
-                im |= ((unsigned)acci[i][j][v] & 0xffu) << (8 * v);
+                re |= (unsigned)(accr[i][j][v] + 127) << (8 * v);
+                im |= (unsigned)(acci[i][j][v] + 127) << (8 * v);
             }
             out[(wave * CTM * CTN + i * CTN + j) * 64 + lane] = uint2{re, im};
         }
@@ -331,25 +336,32 @@ struct CrtRecArgs {
     int n_g, nt, ntri, b;
 };
 
-// the integer with symmetric residues r[i] (|r| <= (m_i - 1) / 2)
-__device__ __forceinline__ double garner(const float (&r)[NMOD]) {
+// The integer with residues rb[i] - 127 (rb: the stored bytes). Digit i is
+// (r_i u_i - sum_{j<i} (W_j u_i mod m_i) v_j) mod m_i, one reduction per
+// digit; digits are folded three at a time in FP32 (exact) and the four
+// groups by Horner's rule in FP64.
+__device__ __forceinline__ double garner(const float (&rb)[NMOD]) {
     float v[NMOD];
-    v[0] = r[0];
+    v[0] = rb[0] - 127.0f;
 #pragma unroll
     for (int i = 1; i < NMOD; ++i) {
         const float mf = (float)CRT_MOD[i];
         const float inv = 1.0f / (float)CRT_MOD[i];
-        float s = r[i];
+        float s = fmaf(rb[i], (float)GT.u[i], -127.0f * (float)GT.u[i]);     // r_i u_i
 #pragma unroll
-        for (int j = 0; j < i; ++j) s = fmaf(-(float)GT.w[i][j], v[j], s);   // |s| < 2^24
-        s = fmaf(-mf, rintf(s * inv), s);                                    // |s| <= 127
-        s *= (float)GT.u[i];                                                 // |s| <= 127^2
-        v[i] = fmaf(-mf, rintf(s * inv), s);
+        for (int j = 0; j < i; ++j) s = fmaf(-(float)GT.wu[i][j], v[j], s);  // |s| < 2^24
+        v[i] = fmaf(-mf, rintf(s * inv), s);                                  // |v_i| <= 127
     }
-    double x = v[NMOD - 1];
-#pragma unroll
-    for (int i = NMOD - 2; i >= 0; --i) x = fma(x, (double)CRT_MOD[i], (double)v[i]);
-    return x;
+    auto fold3 = [&](int i) __attribute__((always_inline)) {   // v_i + m_i (v_i+1 + m_i+1 v_i+2)
+        return fmaf((float)CRT_MOD[i], fmaf((float)CRT_MOD[i + 1], v[i + 2], v[i + 1]), v[i]);
+    };
+    const double g0 = fold3(0), g1 = fold3(3), g2 = fold3(6);
+    const double g3 = fmaf((float)CRT_MOD[9], v[10], v[9]);
+    constexpr double P3 = (double)CRT_MOD[0] * CRT_MOD[1] * CRT_MOD[2];
+    constexpr double P6 = (double)CRT_MOD[3] * CRT_MOD[4] * CRT_MOD[5];
+    constexpr double P9 = (double)CRT_MOD[6] * CRT_MOD[7] * CRT_MOD[8];
+    static_assert(NMOD == 11, "the digit grouping assumes 11 moduli");
+    return fma(fma(fma(g3, P9, g2), P6, g1), P3, g0);
 }
 
 __global__ void __launch_bounds__(256)
@@ -384,8 +396,8 @@ k_crt_recon(CrtRecArgs a) {
             float rr[NMOD], ri[NMOD];
 #pragma unroll
             for (int mi = 0; mi < NMOD; ++mi) {
-                rr[mi] = (float)(int)(signed char)(w[mi].x >> (8 * v));
-                ri[mi] = (float)(int)(signed char)(w[mi].y >> (8 * v));
+                rr[mi] = (float)((w[mi].x >> (8 * v)) & 0xffu);
+                ri[mi] = (float)((w[mi].y >> (8 * v)) & 0xffu);
             }
             const int gp = gp0 + v < n_g ? gp0 + v : n_g - 1;
             const int sh = col_exp(mP, gp) + eq - 2 * (a.b - 1);

@@ -9,7 +9,8 @@
 // One stage is BK = 16 contraction rows of P (BM columns) and Q (BN
 // columns). Wave w loads rows w and w + 8 of both, 64 columns per load, so
 // every load's row is wave-uniform: its segment, its row pointer and the
-// failure-branch selector (SEL: P row taken from palt) are scalar work.
+// failure-branch selector (SEL: P row taken from palt; the selectors are
+// loaded a stage ahead) are scalar work.
 // Columns past the edge read the last column (they only feed outputs past
 // the edge, which are not stored); rows past the end of the contraction are
 // written as zeros with ordinary LDS stores (only the last stage has any).
@@ -81,7 +82,20 @@ __device__ __forceinline__ void ztile_direct(const Segs<NSEG, SEL, SCALE> &t, in
     auto at = [](const double2 *row, unsigned vo) __attribute__((always_inline)) {
         return reinterpret_cast<const double2 *>(reinterpret_cast<const char *>(row) + vo);
     };
-    // rows w and w + 8 of stage st into buf
+    // failure-branch selectors of this wave's rows w and w + 8, loaded one
+    // stage before the rows themselves: a selector loaded and used at once
+    // held every stage's loads (and so its MFMAs) for a memory round trip
+    int selv[2] = {0, 0};
+    auto load_sel = [&](int st) __attribute__((always_inline)) {
+        if constexpr (SEL) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int kk = st * C::BK + wave + 8 * k;
+                selv[k] = kk < ktot ? t.sel[kk] : 0;
+            }
+        }
+    };
+    // rows w and w + 8 of stage st into buf (selectors from load_sel(st))
     auto issue = [&](double2 *buf, int st) __attribute__((always_inline)) {
         double2 *lp = buf;
         double2 *lq = buf + C::BK * C::BM;
@@ -96,7 +110,7 @@ __device__ __forceinline__ void ztile_direct(const Segs<NSEG, SEL, SCALE> &t, in
                 const long long row = kk - s * t.len;
                 const double2 *prow = pick<NSEG>(t.P, s);
                 if constexpr (SEL)
-                    if (t.sel[kk]) prow = t.palt;
+                    if (selv[k]) prow = t.palt;
                 const double2 *qrow = pick<NSEG>(t.Q, s);
                 prow += row * t.ldp;
                 qrow += row * t.ldq;
@@ -228,7 +242,9 @@ __device__ __forceinline__ void ztile_direct(const Segs<NSEG, SEL, SCALE> &t, in
 
     constexpr int BUF = C::BK * (C::BM + C::BN);
     load_scales(qs, 0);
+    load_sel(0);
     issue(lds, 0);
+    load_sel(1);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     for (int s = 0; s < nst; ++s) {
@@ -237,6 +253,7 @@ __device__ __forceinline__ void ztile_direct(const Segs<NSEG, SEL, SCALE> &t, in
             if (s + 1 < nst) {
                 issue(nxt, s + 1);
                 load_scales(qs_next, s + 1);
+                load_sel(s + 2);
             }
             compute(cur, cur + C::BK * C::BM);
         };

@@ -251,22 +251,65 @@ def test_crt_reconstruction_exact():
         assert all(abs(d) <= (m - 1) // 2 for d, m in zip(v, CRT_MODULI))
 
 
-def test_crt_garner_digits_in_float32():
-    # the kernel's digit step t = (t - v_j) c mod m_i in FP32: operands below
-    # 2^24 and the quotient never within rounding of a half-integer
-    worst = 0
+def _garner_tables():
+    """w[i][j] = W_j mod m_i, u[i] = W_i^-1 mod m_i, wu = w u mod m_i (symmetric)."""
+    n = len(CRT_MODULI)
+    w = [[0] * n for _ in range(n)]
+    wu = [[0] * n for _ in range(n)]
+    u = [0] * n
     for i, mi in enumerate(CRT_MODULI):
+        wm = 1
         for j in range(i):
-            c = pow(CRT_MODULI[j], -1, mi)
-            c = c - mi if c > mi // 2 else c
-            for t in range(-(mi - 1) // 2, (mi - 1) // 2 + 1, 7):
-                for vj in (-(CRT_MODULI[j] - 1) // 2, 0, (CRT_MODULI[j] - 1) // 2):
-                    x = (t - vj) * c
-                    worst = max(worst, abs(x))
-                    q = np.rint(np.float32(x) * np.float32(1.0 / mi))
-                    r = np.float32(x) - np.float32(mi) * q
-                    assert r == sym_mod(x, mi)
-    assert worst < 2 ** 24
+            w[i][j] = sym_mod(wm, mi)
+            wm = wm * CRT_MODULI[j] % mi
+        u[i] = sym_mod(pow(wm, -1, mi), mi)
+        for j in range(i):
+            wu[i][j] = sym_mod(w[i][j] * u[i], mi)
+    return w, u, wu
+
+
+def _garner_f32(rbytes):
+    """The reconstruction's arithmetic as the kernel does it, in float32 (every
+    product and sum is an integer below 2^24, so fused and unfused forms
+    agree) and float64: digits, groups of three, Horner."""
+    _, u, wu = _garner_tables()
+    f = np.float32
+    v = [f(rbytes[0]) - f(127)]
+    for i in range(1, len(CRT_MODULI)):
+        mi = f(CRT_MODULI[i])
+        inv = f(1) / mi
+        s = f(rbytes[i]) * f(u[i]) - f(127) * f(u[i])
+        assert abs(float(s)) < 2 ** 24
+        for j in range(i):
+            s = s - f(wu[i][j]) * v[j]
+            assert abs(float(s)) < 2 ** 24
+        v.append(s - mi * np.rint(s * inv))
+    m = [f(x) for x in CRT_MODULI]
+    g = [float(v[i] + m[i] * (v[i + 1] + m[i + 1] * v[i + 2])) for i in (0, 3, 6)]
+    g.append(float(v[9] + m[9] * v[10]))
+    assert all(abs(x) < 2 ** 24 for x in g)
+    P3 = float(CRT_MODULI[0] * CRT_MODULI[1] * CRT_MODULI[2])
+    P6 = float(CRT_MODULI[3] * CRT_MODULI[4] * CRT_MODULI[5])
+    P9 = float(CRT_MODULI[6] * CRT_MODULI[7] * CRT_MODULI[8])
+    return ((g[3] * P9 + g[2]) * P6 + g[1]) * P3 + g[0], [int(x) for x in v]
+
+
+def test_crt_garner_digits_in_float32():
+    """The kernel's FP32 digits equal the exact mixed-radix digits, and its
+    FP64 value is the integer up to the rounding of the last few steps."""
+    rng = np.random.default_rng(9)
+    M = crt_product()
+    half = (M - 1) // 2
+    cases = [0, 1, -1, half, -half, 127, -(half - 5)]
+    cases += [int(x) for x in rng.integers(-2 ** 62, 2 ** 62, 200)]
+    cases += [int(rng.integers(-2 ** 43, 2 ** 43)) * int(rng.integers(1, 2 ** 42)) for _ in range(200)]
+    for x in cases:
+        rbytes = [sym_mod(x, m) + 127 for m in CRT_MODULI]
+        assert all(0 <= r <= 254 for r in rbytes)
+        got, digits = _garner_f32(rbytes)
+        _, exact_digits = garner([r - 127 for r in rbytes])
+        assert digits == exact_digits
+        assert abs(got - x) <= 2.0 ** -50 * max(abs(x), 1)
 
 
 def _crt_dot_columns(P, Q, b):
