@@ -7,12 +7,13 @@
 // with M1, M2 prepared by k_prep (M2 = 1/2 T^BB_a and, on failure,
 // M1 = T^AA_a, both Hermitian, so M^H = M).
 //
-// Each block computes a BM x BN tile of one atom's N_L x N_G output; the
-// contraction runs over the atom's N_L rows (twice for Z). The grid is
-// (N_G tiles, atoms x row tiles, 2 products); Z and W land in the stacked
-// [K][N_G] layout that the large reductions read.
+// Each block computes a BM x BN tile of one atom's N_L x N_G output (one
+// tile covers all of an atom's rows, BM >= N_L); the contraction runs over
+// the atom's N_L rows (twice for Z). The grid is (N_G tiles, atoms x row
+// tiles, 2 products); Z and W land in the stacked [K][N_G] layout that the
+// large reductions read.
 #include "hs_internal.h"
-#include "zmfma_tile.h"
+#include "zmfma_atom.h"
 
 namespace hs {
 
@@ -61,26 +62,23 @@ k_atom(Atoms at, int n_g, int mtiles, const double2 *__restrict__ A,
         tab.Q[1] = tab.Q[0];
     }
 
+    const bool tri = which == 1 && sel[2 * at.K + r0] == 0;
     Acc<C> acc;
-    ztile_run<C>(tab, m0, n, n0, n_g, acc, lds);
+    ztile_atom<C, 2>(tab, m0, n, n0, n_g, tri, acc, lds);
 
     double2 *out = (which == 0 ? Z : W) + (long long)r0 * n_g;
 #pragma unroll
     for (int i = 0; i < C::TM; ++i)
 #pragma unroll
         for (int j = 0; j < C::TN; ++j) {
-            const int g = n0 + acc_col<C>(j);
+            const int g = n0 + atom_col<C>(j);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int l = m0 + acc_row<C>(i, v);
+                const int l = m0 + atom_row<C>(i, v);
                 if (l < n && g < n_g) out[(long long)l * n_g + g] = double2{acc.re[i][j][v], acc.im[i][j][v]};
             }
         }
 }
-
-// Row tile of 64 for N_L <= 64, else 128 (one tile covers an atom's rows).
-using AtomCfg64 = TileCfg<64, 64, 16, 2, 2>;
-using AtomCfg128 = TileCfg<128, 64, 16, 2, 2>;
 
 template <class C>
 hipError_t launch_atom_cfg(const Atoms &at, int n_g, const double2 *A, const double2 *B,
@@ -95,12 +93,18 @@ hipError_t launch_atom_cfg(const Atoms &at, int n_g, const double2 *A, const dou
 
 }  // namespace
 
+// Row tile of 32, 64, 96 or 128 (the smallest that covers the largest N_L),
+// 128 columns.
 hipError_t launch_atom(const Atoms &at, int n_g, const double2 *A, const double2 *B,
                        const double2 *T_AB, const double2 *M1, const double2 *M2,
                        const int *sel, double2 *Z, double2 *W, hipStream_t st) {
+    if (at.max_nl <= 32)
+        return launch_atom_cfg<AtomCfg<1, 2, 16>>(at, n_g, A, B, T_AB, M1, M2, sel, Z, W, st);
     if (at.max_nl <= 64)
-        return launch_atom_cfg<AtomCfg64>(at, n_g, A, B, T_AB, M1, M2, sel, Z, W, st);
-    return launch_atom_cfg<AtomCfg128>(at, n_g, A, B, T_AB, M1, M2, sel, Z, W, st);
+        return launch_atom_cfg<AtomCfg<2, 2, 16>>(at, n_g, A, B, T_AB, M1, M2, sel, Z, W, st);
+    if (at.max_nl <= 96)
+        return launch_atom_cfg<AtomCfg<3, 2, 16>>(at, n_g, A, B, T_AB, M1, M2, sel, Z, W, st);
+    return launch_atom_cfg<AtomCfg<4, 2, 16>>(at, n_g, A, B, T_AB, M1, M2, sel, Z, W, st);
 }
 
 }  // namespace hs

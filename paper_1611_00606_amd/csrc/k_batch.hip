@@ -3,7 +3,8 @@
 // with its failure test, prep_atom.h) and every atom's products
 //   Z_a = T_AB,a^H A_a + M2_a^H B_a,   W_a = M1_a^H A_a   (Y_a or X_a)
 // with the tile shape of each atom's products chosen per N_L (a table filled
-// by the autotuner in hs_tune.hip, or the built-in choice below).
+// by the autotuner in hs_tune.hip, or the built-in choice below), on the
+// per-atom tile engine of zmfma_atom.h.
 //
 // Work items, taken in order from one atomic counter by a grid of one
 // 8-wave block per CU:
@@ -19,7 +20,7 @@
 // With the preparation done elsewhere (the resident context caches it), the
 // launch has product items only and nothing waits.
 #include "prep_atom.h"
-#include "zmfma_tile.h"
+#include "zmfma_atom.h"
 
 namespace hs {
 
@@ -27,16 +28,16 @@ namespace {
 
 constexpr int BT = 512;   // threads of the persistent block (8 waves)
 
-// Candidate tile shapes (BM rows of the atom's N_L x BN columns of N_G).
-// At most four 16x16 blocks per wave: with the item loop's own state, a
-// larger wave tile does not fit the 256 registers of a two-wave-per-SIMD
-// launch and spills.
-using Cfg0 = TileCfg<32, 128, 16, 1, 8>;
-using Cfg1 = TileCfg<32, 256, 16, 1, 8>;
-using Cfg2 = TileCfg<64, 64, 16, 2, 4>;
-using Cfg3 = TileCfg<64, 128, 16, 2, 4>;
-using Cfg4 = TileCfg<128, 64, 16, 4, 2>;
-using Cfg5 = TileCfg<128, 64, 16, 2, 4>;
+// Candidate tile shapes (BM rows of the atom's N_L x BN columns of N_G):
+// 32, 64, 96 or 128 rows by 128 columns, and 32 or 64 rows by 256 columns
+// (stages of 8 rows, so that two stages fit the LDS). At most eight 16x16
+// blocks per wave (128 accumulator registers).
+using Cfg0 = AtomCfg<1, 2, 16>;   //  32 x 128
+using Cfg1 = AtomCfg<2, 2, 16>;   //  64 x 128
+using Cfg2 = AtomCfg<3, 2, 16>;   //  96 x 128
+using Cfg3 = AtomCfg<4, 2, 16>;   // 128 x 128
+using Cfg4 = AtomCfg<1, 4, 8>;    //  32 x 256
+using Cfg5 = AtomCfg<2, 4, 8>;    //  64 x 256
 static_assert(Cfg0::NT == BT && Cfg1::NT == BT && Cfg2::NT == BT && Cfg3::NT == BT &&
                   Cfg4::NT == BT && Cfg5::NT == BT,
               "every tile shape runs on the whole persistent block");
@@ -101,17 +102,17 @@ __device__ __forceinline__ void product_tile(int which, bool failing, int r0, in
         tab.Q[1] = tab.Q[0];
     }
     Acc<C> acc;
-    ztile_run<C>(tab, m0, n, n0, n_g, acc, lds);
+    ztile_atom<C, 2>(tab, m0, n, n0, n_g, which == 1 && !failing, acc, lds);
 
     double2 *out = (which == 0 ? Z : W) + (long long)r0 * n_g;
 #pragma unroll
     for (int i = 0; i < C::TM; ++i)
 #pragma unroll
         for (int j = 0; j < C::TN; ++j) {
-            const int g = n0 + acc_col<C>(j);
+            const int g = n0 + atom_col<C>(j);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int l = m0 + acc_row<C>(i, v);
+                const int l = m0 + atom_row<C>(i, v);
                 if (l < n && g < n_g) out[(long long)l * n_g + g] = double2{acc.re[i][j][v], acc.im[i][j][v]};
             }
         }
@@ -279,11 +280,10 @@ int tile_shape(int id, int *bm, int *bn) {
     return 0;
 }
 
-// Built-in choice: the 8192-output shape with the least row padding
-// (32 x 256 or 64 x 128; on a tie the taller tile).
+// Built-in choice: the 128-column tile with the fewest rows that cover N_L
+// (one row tile per atom).
 int default_tile(int nl) {
-    const int pad32 = (nl + 31) / 32 * 32, pad64 = (nl + 63) / 64 * 64;
-    return pad32 < pad64 ? 1 : 3;
+    return nl <= 32 ? 0 : nl <= 64 ? 1 : nl <= 96 ? 2 : 3;
 }
 
 void BatchPlan::make(const AtomPlan &p, int n_g, const unsigned char *cfg_table) {

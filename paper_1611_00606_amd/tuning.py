@@ -3,8 +3,8 @@
 `autotune` measures every batched tile shape per N_L on the current device
 (hs_autotune_atoms in the library does the timing) and returns the hs_tuning
 table to pass as `tuning=` to hs_build_ex / DeviceBuild / Context.build. A
-JSON cache file keyed by device architecture, N_G and N_L keeps the choice
-across processes, so the measurement runs once per shape.
+JSON cache file keyed by device architecture, N_G and N_L keeps the chosen
+shape (as "BMxBN") across processes, so the measurement runs once per N_L.
 """
 
 from __future__ import annotations
@@ -35,9 +35,17 @@ def tuning_from_table(table: Dict[int, int]) -> B.hs_tuning:
 
 def default_shape(nl: int) -> int:
     """The library's built-in shape id for N_L (used when no table is given):
-    32 x 256 or 64 x 128, whichever pads the atom's rows less (ties: 64)."""
-    pad32, pad64 = -(-nl // 32) * 32, -(-nl // 64) * 64
-    return 1 if pad32 < pad64 else 3
+    the 128-column tile with the fewest rows (32, 64, 96, 128) covering N_L."""
+    return 0 if nl <= 32 else 1 if nl <= 64 else 2 if nl <= 96 else 3
+
+
+def _shape_id(bm_bn: str) -> Optional[int]:
+    """Shape id of a cached "BMxBN" entry, or None when the library has no
+    such shape (a cache written for another shape set is measured again)."""
+    for c, s in shapes().items():
+        if isinstance(bm_bn, str) and bm_bn == f"{s[0]}x{s[1]}":
+            return c
+    return None
 
 
 def autotune(nl_values: Iterable[int], n_g: int, reps: int = 3,
@@ -55,9 +63,10 @@ def autotune(nl_values: Iterable[int], n_g: int, reps: int = 3,
     table, report, todo = {}, {}, []
     for v in vals:
         k = f"{key_base}/N_L={v}"
-        if k in stored:
-            table[v] = int(stored[k])
-            report[v] = {"shape": table[v], "bm_bn": B.hs_tile_config(table[v]), "ms": None}
+        c = _shape_id(stored.get(k))
+        if c is not None:
+            table[v] = c
+            report[v] = {"shape": c, "bm_bn": B.hs_tile_config(c), "ms": None}
         else:
             todo.append(v)
     if todo:
@@ -66,7 +75,8 @@ def autotune(nl_values: Iterable[int], n_g: int, reps: int = 3,
             table[v] = int(t.cfg[v])
             report[v] = {"shape": table[v], "bm_bn": B.hs_tile_config(table[v]),
                          "ms": [round(float(x), 4) for x in ms[i]]}
-            stored[f"{key_base}/N_L={v}"] = table[v]
+            bm, bn = B.hs_tile_config(table[v])
+            stored[f"{key_base}/N_L={v}"] = f"{bm}x{bn}"
         if cache:
             d = os.path.dirname(os.path.abspath(cache))
             os.makedirs(d, exist_ok=True)

@@ -178,8 +178,14 @@ def test_split_mode_workspace():
 def test_tile_configs():
     shapes = [P.hs_tile_config(c) for c in range(P.HS_NUM_TILE_CONFIGS)]
     assert all(s is not None for s in shapes)
+    assert len(set(shapes)) == len(shapes)
     for bm, bn in shapes:
-        assert bm % 16 == 0 and bn % 16 == 0 and bm * bn <= 8192
+        assert bm % 32 == 0 and bm <= 128 and bn in (128, 256)
+    # the built-in choice: the fewest 128-column rows that cover N_L
+    from paper_1611_00606_amd.tuning import default_shape as ds
+    for v in range(1, 129):
+        bm, bn = shapes[ds(v)]
+        assert bn == 128 and bm >= v and bm - 32 < v
     assert P.hs_tile_config(-1) is None and P.hs_tile_config(P.HS_NUM_TILE_CONFIGS) is None
     from paper_1611_00606_amd.tuning import default_shape, tuning_from_table
     assert all(0 <= default_shape(v) < P.HS_NUM_TILE_CONFIGS for v in range(1, 129))
