@@ -136,16 +136,22 @@ size_t AtomPlan::atom_bytes() const {
 }
 
 size_t AtomPlan::kpoint_bytes(int n_g, int mode) const {
-    size_t b = 2 * align_up(16 * (size_t)K * (size_t)n_g) + BatchBufs::bytes(n_atoms);
+    size_t b = 2 * align_up(16 * (size_t)K * (size_t)n_g) + BatchBufs::bytes(n_atoms, n_g);
     if (split_mode(mode))
         b += NSPLIT * (align_up(slice_bytes(mode, K, n_g)) + align_up(8 * (size_t)n_g));
     if (mode == HS_SPLIT_I8_CRT) b += align_up(crt_work_bytes(n_g));
     return b;
 }
 
-size_t BatchBufs::bytes(int n_atoms) {
+long long BatchBufs::max_tiles(int n_atoms, int n_g) {
+    return (long long)n_atoms * ((HS_MAX_NL + ATOM_TILE_MIN_BM - 1) / ATOM_TILE_MIN_BM) *
+           ((n_g + ATOM_TILE_MIN_BN - 1) / ATOM_TILE_MIN_BN);
+}
+
+size_t BatchBufs::bytes(int n_atoms, int n_g) {
     return align_up(sizeof(int) * (size_t)n_atoms) + align_up(sizeof(int) * (size_t)(n_atoms + 1)) +
-           align_up(2 * sizeof(int)) + align_up(2 * sizeof(int) * (size_t)n_atoms);
+           align_up(2 * sizeof(int)) + align_up(2 * sizeof(int) * (size_t)n_atoms) +
+           align_up(sizeof(int) * (size_t)max_tiles(n_atoms, n_g));
 }
 
 void BatchBufs::carve(int n_atoms, char *base) {
@@ -157,6 +163,8 @@ void BatchBufs::carve(int n_atoms, char *base) {
     ctrl = reinterpret_cast<int *>(base + o);
     o += align_up(2 * sizeof(int));
     flags = reinterpret_cast<int *>(base + o);
+    o += align_up(2 * sizeof(int) * (size_t)n_atoms);
+    ipos = reinterpret_cast<int *>(base + o);
 }
 
 void AtomBufs::carve(const AtomPlan &p, char *base) {
@@ -190,7 +198,7 @@ void KpointBufs::carve(const AtomPlan &p, int n_g, int mode, char *base) {
     W = reinterpret_cast<double2 *>(base + half);
     size_t o = 2 * half;
     batch.carve(p.n_atoms, base + o);
-    o += BatchBufs::bytes(p.n_atoms);
+    o += BatchBufs::bytes(p.n_atoms, n_g);
     for (int i = 0; i < NSPLIT; ++i) {
         sl[i] = nullptr;
         mx[i] = nullptr;

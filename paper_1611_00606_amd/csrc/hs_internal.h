@@ -172,13 +172,18 @@ struct AtomBufs {
 };
 
 // Batched per-atom stage (k_batch.hip): item tables of one launch.
+// Every tile shape has at least ATOM_TILE_MIN_BM rows and ATOM_TILE_MIN_BN
+// columns, which bounds the product tiles per atom (and so ipos).
+constexpr int ATOM_TILE_MIN_BM = 32, ATOM_TILE_MIN_BN = 128;
 struct BatchBufs {
     int *perm;    // [N_A]
     int *zoff;    // [N_A + 1]
     int *ctrl;    // [2]
     int *flags;   // [2 N_A]
-    static size_t bytes(int n_atoms);
-    void carve(int n_atoms, char *base);
+    int *ipos;    // [max_tiles(N_A, N_G)] position of each product tile
+    static long long max_tiles(int n_atoms, int n_g);
+    static size_t bytes(int n_atoms, int n_g);
+    void carve(int n_atoms, char *base);   // ipos last
 };
 // Host plan: tile shape per N_L, atom order (N_L descending) and the first
 // product tile of each position.

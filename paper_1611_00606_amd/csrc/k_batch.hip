@@ -42,6 +42,13 @@ static_assert(Cfg0::NT == BT && Cfg1::NT == BT && Cfg2::NT == BT && Cfg3::NT == 
                   Cfg4::NT == BT && Cfg5::NT == BT,
               "every tile shape runs on the whole persistent block");
 static_assert(HS_NUM_TILE_CONFIGS == 6, "tile table and candidate list agree");
+static_assert(Cfg0::BM >= ATOM_TILE_MIN_BM && Cfg1::BM >= ATOM_TILE_MIN_BM &&
+                  Cfg2::BM >= ATOM_TILE_MIN_BM && Cfg3::BM >= ATOM_TILE_MIN_BM &&
+                  Cfg4::BM >= ATOM_TILE_MIN_BM && Cfg5::BM >= ATOM_TILE_MIN_BM &&
+                  Cfg0::BN >= ATOM_TILE_MIN_BN && Cfg1::BN >= ATOM_TILE_MIN_BN &&
+                  Cfg2::BN >= ATOM_TILE_MIN_BN && Cfg3::BN >= ATOM_TILE_MIN_BN &&
+                  Cfg4::BN >= ATOM_TILE_MIN_BN && Cfg5::BN >= ATOM_TILE_MIN_BN,
+              "the tile-position table is sized for these minima");
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int TILE_LDS = 16 * cmax(cmax(cmax(Cfg0::LDS_ELEMS, Cfg1::LDS_ELEMS),
@@ -61,6 +68,7 @@ struct BatchArgs {
     double2 *Z, *W;
     const int *perm;   // [N_A] atom at each position
     const int *zoff;   // [N_A + 1] first product tile of each position
+    const int *ipos;   // [nz] position of each product tile
     int *ctrl;         // [0] item counter, [1] waits that ran out
     int *flags;        // [2 N_A] M2 ready, M1 ready
     int n_g, nz, do_factor;
@@ -152,12 +160,7 @@ k_batch(BatchArgs args) {
                     kind = 2;
                     j -= nz;
                 }
-                int lo = 0, hi = n_atoms - 1;   // last position with zoff <= j
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (args.zoff[mid] <= j) lo = mid;
-                    else hi = mid - 1;
-                }
+                const int lo = args.ipos[j];   // position of product tile j
                 atom = args.perm[lo];
                 loc = j - args.zoff[lo];
                 if (args.do_factor &&
@@ -247,6 +250,13 @@ k_batch_tables(BatchChunk c, int *perm, int *zoff, int *ctrl, int *flags) {
     if (threadIdx.x == 0 && c.last) zoff[c.n_atoms] = c.nz;
 }
 
+// Position of every product tile (one block per position): the item loop
+// then finds a tile's atom with one load instead of a search over zoff.
+__global__ void __launch_bounds__(256) k_batch_ipos(const int *zoff, int *ipos) {
+    const int p = blockIdx.x;
+    for (int j = zoff[p] + threadIdx.x; j < zoff[p + 1]; j += 256) ipos[j] = p;
+}
+
 // After a launch with preparation items: a wait that ran out marks the build.
 __global__ void __launch_bounds__(256) k_batch_check(const int *ctrl, int *info, int n_atoms) {
     if (ctrl[1] == 0) return;
@@ -314,7 +324,8 @@ bool BatchPlan::valid(const AtomPlan &p, const unsigned char *cfg_table) {
 
 hipError_t launch_batch(const AtomPlan &p, const Atoms &at, const BatchPlan &bp, int n_g,
                         bool do_factor, const BatchIO &io, const BatchBufs &bb, hipStream_t st) {
-    if (bp.nz > (1LL << 30)) return hipErrorInvalidValue;
+    if (bp.nz > (1LL << 30) || bp.nz > BatchBufs::max_tiles(p.n_atoms, n_g))
+        return hipErrorInvalidValue;
     for (int p0 = 0; p0 < p.n_atoms; p0 += BT_CHUNK) {
         BatchChunk c;
         c.p0 = p0;
@@ -331,6 +342,8 @@ hipError_t launch_batch(const AtomPlan &p, const Atoms &at, const BatchPlan &bp,
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
+    hipLaunchKernelGGL(k_batch_ipos, dim3(p.n_atoms), dim3(256), 0, st, bb.zoff, bb.ipos);
+    if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
     BatchArgs a;
     a.at = at;
     a.T_AA = io.T_AA;
@@ -348,6 +361,7 @@ hipError_t launch_batch(const AtomPlan &p, const Atoms &at, const BatchPlan &bp,
     a.W = io.W;
     a.perm = bb.perm;
     a.zoff = bb.zoff;
+    a.ipos = bb.ipos;
     a.ctrl = bb.ctrl;
     a.flags = bb.flags;
     a.n_g = n_g;
