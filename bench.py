@@ -516,7 +516,8 @@ def serving_bench(seed: int, sizes, data, n_slots: int = 4, arena_gb: float = 24
     out["latency_samples"] = len(reqs) * streams
     out["offered_rate_per_s"] = [round(x, 3) for x in offered]
     out.update({
-        "mode": {0: "fp64", 1: "split_f16", 2: "split_i8", 3: "fp64_3m", 4: "split_bf16"}[mode],
+        "mode": {0: "fp64", 1: "split_f16", 2: "split_i8", 3: "fp64_3m", 4: "split_bf16",
+                 5: "split_i8_crt"}[mode],
         "workload": "64 requests, N_A=64 atoms, N_L=64, N_G uniform in [1500, 9000], each with "
                     "its own seeded A, B in pinned host memory, Poisson arrivals",
         "arrival_rate_per_s": rate,   # nominal Poisson rate; offered_rate_per_s is realized
@@ -903,10 +904,10 @@ def main():
               flush=True)
         from hs_inputs import SERVING
         sizes, sdata = serving_inputs(args.seed, SERVING["N_A"] * SERVING["N_L"])
-        modes = [0] + ([1, 2, 3] if not args.no_split else [])
+        modes = [0] + ([1, 2, 3, 5] if not args.no_split else [])
         for mode in modes:
             key = {0: "serving", 1: "serving_split_f16", 2: "serving_split_i8",
-                   3: "serving_fp64_3m"}[mode]
+                   3: "serving_fp64_3m", 5: "serving_split_i8_crt"}[mode]
             print(f"bench: serving stream, {key}", file=sys.stderr, flush=True)
             out[key], serving_samples[key] = serving_bench(args.seed, sizes, sdata, mode=mode)
         print("bench: serving stream, bypass admission", file=sys.stderr, flush=True)

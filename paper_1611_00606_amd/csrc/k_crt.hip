@@ -142,9 +142,11 @@ k_residue(SliceSrc src, int K, int n_g, int groups, int b) {
 //
 // Measured at N_G = 8000 (K = 8100): against 8 waves of 64 x 32 outputs in
 // 128-row stages (one block per CU) this shape reads a third less from LDS
-// per MFMA and is 9% faster; deeper pipelines (3 or 4 buffers, up to three
+// per MFMA and is 9% faster; deeper pipelines (3 to 5 buffers, up to four
 // stages in flight) are not faster: the kernel runs INT8 MFMA at a reduced
-// clock (about 1.8 GHz by the cycle counters), not waiting on operands.
+// clock (about 1.74 GHz by the cycle counters), not waiting on operands.
+// Bands of 8 tile columns in the tile order (64 tiles resident per XCD
+// share 8 row and 8 column panels) fetch 15% less than bands of 4.
 
 constexpr int CB = 128;                    // tile rows (g') and columns (g)
 constexpr int CWM = 2, CWN = 2;            // waves

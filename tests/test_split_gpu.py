@@ -167,3 +167,44 @@ def test_bf16_slices_equal_f16_slices(name):
     Hf, Sf, i_f = _run(p, 1).results()
     Hb, Sb, i_b = _run(p, 4).results()
     assert np.array_equal(Hf, Hb) and np.array_equal(Sf, Sb) and np.array_equal(i_f, i_b)
+
+
+def _integer_problem(seed=21):
+    """Small Gaussian-integer operands, every T^AA_a negative definite (the
+    failure branch, so no Cholesky factor enters), U of integer modulus and
+    T^BB with even diagonal: every operand the reductions see is an exact
+    dyadic number and every product and sum is an integer far below 2^53."""
+    rng = np.random.default_rng(seed)
+    p = make_problem(4, 12, 300, seed=seed, fail_atoms=[0, 1, 2, 3])
+    gi = lambda *s: (rng.integers(-3, 4, s) + 1j * rng.integers(-3, 4, s)).astype(complex)  # noqa: E731
+    p.A[:] = gi(*p.A.shape)
+    p.B[:] = gi(*p.B.shape)
+    p.T_AB[:] = gi(*p.T_AB.shape)
+    units = np.array([1, -1, 1j, -1j, 2, 3 + 4j, -4 + 3j])   # |u|^2 a perfect square
+    p.U[:] = units[rng.integers(0, len(units), p.K)]
+    for a in range(p.N_A):
+        n = int(p.nl[a])
+        h = gi(n, n)
+        h = h + h.conj().T                      # Hermitian, even real diagonal
+        p.set_t_block("T_AA", a, h - 40.0 * np.eye(n))
+        t = gi(n, n)
+        p.set_t_block("T_BB", a, t + t.conj().T)
+    return p
+
+
+@pytest.mark.parametrize("mode", [0, 3, 5])
+def test_exact_on_integer_operands(mode):
+    """FP64, 3M and the modular form are exact on dyadic operands whose
+    products fit the formats: H and S bitwise equal to the oracle's exact
+    values (the modular form rounds its operands to 36-bit integers, which
+    these hold exactly, so its residue arithmetic and reconstruction are
+    pinned to the last bit)."""
+    p = _integer_problem()
+    r = _run(p, mode)
+    H, S, info = r.results()
+    Hr = O.hamiltonian(p.A, p.B, p.T_AA, p.T_AB, p.T_BB, p.nl)
+    Sr = O.overlap(p.A, p.B, p.U, p.nl)
+    assert np.all(Hr.real == np.round(Hr.real * 2) / 2) and np.all(Sr.imag == np.round(Sr.imag))
+    assert np.array_equal(info, _expected_info(p))
+    assert np.array_equal(S, Sr), np.max(np.abs(S - Sr))
+    assert np.array_equal(H, Hr), np.max(np.abs(H - Hr))
