@@ -151,7 +151,7 @@ long long BatchBufs::max_tiles(int n_atoms, int n_g) {
 size_t BatchBufs::bytes(int n_atoms, int n_g) {
     return align_up(sizeof(int) * (size_t)n_atoms) + align_up(sizeof(int) * (size_t)(n_atoms + 1)) +
            align_up(2 * sizeof(int)) + align_up(2 * sizeof(int) * (size_t)n_atoms) +
-           align_up(sizeof(int) * (size_t)max_tiles(n_atoms, n_g));
+           align_up(2 * sizeof(int) * (size_t)max_tiles(n_atoms, n_g));
 }
 
 void BatchBufs::carve(int n_atoms, char *base) {
@@ -164,7 +164,7 @@ void BatchBufs::carve(int n_atoms, char *base) {
     o += align_up(2 * sizeof(int));
     flags = reinterpret_cast<int *>(base + o);
     o += align_up(2 * sizeof(int) * (size_t)n_atoms);
-    ipos = reinterpret_cast<int *>(base + o);
+    tiles = reinterpret_cast<int *>(base + o);
 }
 
 void AtomBufs::carve(const AtomPlan &p, char *base) {

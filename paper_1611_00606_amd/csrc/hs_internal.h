@@ -173,17 +173,17 @@ struct AtomBufs {
 
 // Batched per-atom stage (k_batch.hip): item tables of one launch.
 // Every tile shape has at least ATOM_TILE_MIN_BM rows and ATOM_TILE_MIN_BN
-// columns, which bounds the product tiles per atom (and so ipos).
+// columns, which bounds the product tiles per atom (and so the tile table).
 constexpr int ATOM_TILE_MIN_BM = 32, ATOM_TILE_MIN_BN = 128;
 struct BatchBufs {
     int *perm;    // [N_A]
     int *zoff;    // [N_A + 1]
     int *ctrl;    // [2]
     int *flags;   // [2 N_A]
-    int *ipos;    // [max_tiles(N_A, N_G)] position of each product tile
+    int *tiles;   // [2 max_tiles(N_A, N_G)] atom, tile within the atom of each product tile
     static long long max_tiles(int n_atoms, int n_g);
     static size_t bytes(int n_atoms, int n_g);
-    void carve(int n_atoms, char *base);   // ipos last
+    void carve(int n_atoms, char *base);   // tiles last
 };
 // Host plan: tile shape per N_L, atom order (N_L descending) and the first
 // product tile of each position.

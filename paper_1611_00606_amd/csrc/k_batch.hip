@@ -67,8 +67,7 @@ struct BatchArgs {
     int *sel, *info;
     double2 *Z, *W;
     const int *perm;   // [N_A] atom at each position
-    const int *zoff;   // [N_A + 1] first product tile of each position
-    const int *ipos;   // [nz] position of each product tile
+    const int *tiles;  // [2 nz] atom and tile index within the atom of each product tile
     int *ctrl;         // [0] item counter, [1] waits that ran out
     int *flags;        // [2 N_A] M2 ready, M1 ready
     int n_g, nz, do_factor;
@@ -126,18 +125,22 @@ __device__ __forceinline__ void product_tile(int which, bool failing, int r0, in
         }
 }
 
-__device__ __forceinline__ bool wait_flag(const int *f) {
+// The flag's value once set (nonzero), or 0 if the wait ran out.
+__device__ __forceinline__ int wait_flag(const int *f) {
     for (int i = 0; i < SPIN_LIMIT; ++i) {
-        if (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) return true;
+        if (const int v = __hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) return v;
         __builtin_amdgcn_s_sleep(8);
     }
-    return false;
+    return 0;
 }
 
 __global__ void __launch_bounds__(BT)
 k_batch(BatchArgs args) {
     __shared__ __align__(16) char lds[BATCH_LDS];
-    __shared__ int s_job[3];   // kind (-1 done, 0 prep, 1 Z, 2 W), atom, tile
+    // kind (-1 done, 0 prep, 1 Z, 2 W, 3 skipped), atom, tile, and for
+    // tiles the atom's first row, N_L, first element of its blocks, and
+    // whether its Cholesky failed
+    __shared__ int s_job[7];
 
     const Atoms at = args.at;
     const int n_atoms = at.n_atoms;
@@ -145,11 +148,15 @@ k_batch(BatchArgs args) {
     const int nf = args.do_factor ? n_atoms : 0;
     const int total = nf + 2 * nz;
 
+    // Thread 0 claims and decodes the next item: the counter, then the tile
+    // table, then the atom's offsets together with its ready flag (whose
+    // value also tells whether the atom's Cholesky failed), so three
+    // dependent memory round trips stand between two items.
     for (;;) {
         __syncthreads();   // the previous item is done with LDS and s_job
         if (threadIdx.x == 0) {
             const int it = atomicAdd(args.ctrl, 1);
-            int kind = -1, atom = 0, loc = 0;
+            int kind = -1, atom = 0, loc = 0, r0 = 0, n = 0, t0 = 0, fail = 0;
             if (it < nf) {
                 kind = 0;
                 atom = args.perm[it];
@@ -160,18 +167,30 @@ k_batch(BatchArgs args) {
                     kind = 2;
                     j -= nz;
                 }
-                const int lo = args.ipos[j];   // position of product tile j
-                atom = args.perm[lo];
-                loc = j - args.zoff[lo];
-                if (args.do_factor &&
-                    !wait_flag(args.flags + (kind == 1 ? atom : n_atoms + atom))) {
-                    atomicAdd(args.ctrl + 1, 1);
-                    kind = 3;   // skipped
+                atom = args.tiles[2 * j];
+                loc = args.tiles[2 * j + 1];
+                r0 = at.row_off[atom];
+                n = at.row_off[atom + 1] - r0;
+                t0 = at.t_off[atom];
+                if (args.do_factor) {
+                    const int f = wait_flag(args.flags + (kind == 1 ? atom : n_atoms + atom));
+                    if (!f) {
+                        atomicAdd(args.ctrl + 1, 1);
+                        kind = 3;   // skipped
+                    }
+                    fail = f == 2;
+                } else if (kind == 2) {
+                    // prepared before the launch: the failure test's result is in sel
+                    fail = args.sel[2 * at.K + r0] != 0;
                 }
             }
             s_job[0] = kind;
             s_job[1] = atom;
             s_job[2] = loc;
+            s_job[3] = r0;
+            s_job[4] = n;
+            s_job[5] = t0;
+            s_job[6] = fail;
         }
         __syncthreads();
         const int kind = s_job[0], atom = s_job[1], loc = s_job[2];
@@ -189,12 +208,12 @@ k_batch(BatchArgs args) {
         // acquire's cache invalidation acts on the CU's and the XCD's caches,
         // which all waves of the block share). A per-wave acquire of the same
         // flag cost one more memory round trip per item (6% of the stage).
-        const int r0 = at.row_off[atom];
-        const int n = at.row_off[atom + 1] - r0;
-        const long long t0 = at.t_off[atom];
+        const int r0 = s_job[3];
+        const int n = s_job[4];
+        const long long t0 = s_job[5];
         const int which = kind - 1;
         // W tiles of an atom with a Cholesky factor contract a triangle only
-        const bool failing = which == 1 && args.sel[2 * at.K + r0] != 0;
+        const bool failing = which == 1 && s_job[6] != 0;
         double2 *tl = reinterpret_cast<double2 *>(lds);
         switch (args.cfg[n]) {
             case 0:
@@ -250,11 +269,17 @@ k_batch_tables(BatchChunk c, int *perm, int *zoff, int *ctrl, int *flags) {
     if (threadIdx.x == 0 && c.last) zoff[c.n_atoms] = c.nz;
 }
 
-// Position of every product tile (one block per position): the item loop
-// then finds a tile's atom with one load instead of a search over zoff.
-__global__ void __launch_bounds__(256) k_batch_ipos(const int *zoff, int *ipos) {
+// Atom and tile index within the atom of every product tile (one block per
+// position): the item loop then decodes a tile with one load instead of a
+// search over zoff.
+__global__ void __launch_bounds__(256) k_batch_tile_index(const int *perm, const int *zoff,
+                                                          int *tiles) {
     const int p = blockIdx.x;
-    for (int j = zoff[p] + threadIdx.x; j < zoff[p + 1]; j += 256) ipos[j] = p;
+    const int atom = perm[p];
+    for (int j = zoff[p] + threadIdx.x; j < zoff[p + 1]; j += 256) {
+        tiles[2 * j] = atom;
+        tiles[2 * j + 1] = j - zoff[p];
+    }
 }
 
 // After a launch with preparation items: a wait that ran out marks the build.
@@ -342,7 +367,8 @@ hipError_t launch_batch(const AtomPlan &p, const Atoms &at, const BatchPlan &bp,
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_batch_ipos, dim3(p.n_atoms), dim3(256), 0, st, bb.zoff, bb.ipos);
+    hipLaunchKernelGGL(k_batch_tile_index, dim3(p.n_atoms), dim3(256), 0, st, bb.perm, bb.zoff,
+                       bb.tiles);
     if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
     BatchArgs a;
     a.at = at;
@@ -360,8 +386,7 @@ hipError_t launch_batch(const AtomPlan &p, const Atoms &at, const BatchPlan &bp,
     a.Z = io.Z;
     a.W = io.W;
     a.perm = bb.perm;
-    a.zoff = bb.zoff;
-    a.ipos = bb.ipos;
+    a.tiles = bb.tiles;
     a.ctrl = bb.ctrl;
     a.flags = bb.flags;
     a.n_g = n_g;

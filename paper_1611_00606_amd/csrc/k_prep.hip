@@ -1,4 +1,4 @@
-// Per-atom preparation, one 256-thread block per atom: the Cholesky of
+// Per-atom preparation, one 512-thread block per atom: the Cholesky of
 // T^AA_a with failure detection and the operand forms of the per-atom
 // products (the routine itself is in prep_atom.h).
 #include "prep_atom.h"
@@ -7,7 +7,7 @@ namespace hs {
 
 namespace {
 
-constexpr int PREP_THREADS = 256;
+constexpr int PREP_THREADS = 512;
 
 __global__ void __launch_bounds__(PREP_THREADS)
 k_prep(Atoms at, const double2 *__restrict__ T_AA, const double2 *__restrict__ T_BB,

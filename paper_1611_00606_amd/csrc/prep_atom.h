@@ -7,11 +7,12 @@
 // factorization may fail numerically), and the operand forms used by the
 // per-atom products.
 //
-// The lower triangle of T^AA_a is held packed (row-major lower, element (i,k)
-// at i(i+1)/2 + k) in LDS: for N_L = 128 that is 8256 complex values =
-// 129 KiB, inside gfx950's 160 KiB of LDS per CU. The factorization
-// (chol_packed) is right-looking; a pivot that is not > 0 (NaN included)
-// stops it and sets info = j+1, the LAPACK zpotrf convention.
+// The lower triangle of T^AA_a is spread over the block's registers (entry
+// e = i(i+1)/2 + k of the packed triangle, k <= i, in slot e / NT of thread
+// e % NT; for N_L = 128, 17 entries per thread of a 512-thread block); only
+// the current column passes through LDS. The factorization (chol_atom) is
+// right-looking with one barrier per column; a pivot that is not > 0 (NaN
+// included) stops it and sets info = j+1, the LAPACK zpotrf convention.
 #pragma once
 
 #include "hs_internal.h"
@@ -20,17 +21,16 @@
 namespace hs {
 
 constexpr int PACKED_MAX = HS_MAX_NL * (HS_MAX_NL + 1) / 2;
-// LDS the routine needs: packed triangle, then the diagonal of C (doubles)
-constexpr int PREP_LDS_BYTES = PACKED_MAX * 16 + HS_MAX_NL * 8;
-
-__device__ __forceinline__ int pidx(int i, int k) { return i * (i + 1) / 2 + k; }
+// LDS the routine needs: two column buffers of HS_MAX_NL complex values
+constexpr int PREP_LDS_BYTES = 2 * HS_MAX_NL * 16;
 
 // Publishes this block's global writes to every other block on the device,
-// then sets *flag (a 0 -> 1 ready flag) with release semantics.
-__device__ __forceinline__ void publish(int *flag) {
+// then sets *flag (a ready flag, 0 until then) to value (nonzero) with
+// release semantics.
+__device__ __forceinline__ void publish(int *flag, int value) {
     __threadfence();
     __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) __hip_atomic_store(flag, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Hermitian n x n block (row-major, element (i,k)) from the lower triangle of
@@ -56,59 +56,87 @@ __device__ __forceinline__ void hermitian_from_lower(const double2 *__restrict__
     }
 }
 
-// Right-looking Cholesky of the packed lower triangle L (n x n, element
-// (i,k) at pidx(i,k)) in LDS by one block of NT threads (every thread calls
-// it). At step j the pivot d_j = T_jj - sum_{k<j} |C_jk|^2 has already been
-// accumulated into the diagonal entry; the column below it is divided by
-// sqrt(d_j) and the trailing triangle receives -C_ij conj(C_kj). On return
-// the entries below the diagonal hold C, diag[j] = C_jj, and the result is
-// 0 or the 1-based index of the first pivot that is not > 0 (NaN included),
-// at which the factorization stopped.
+// Right-looking Cholesky of the n x n Hermitian block t (row-major; its lower
+// triangle is read) by one block of NT threads (every thread calls it), the
+// triangle held in registers as described above. Before step j every entry
+// (i, k), k >= j, holds L_ik = t_ik - sum_{m<j} C_im conj(C_km), and column j
+// (rows i >= j) is also in the LDS buffer col[j & 1]. Step j tests the pivot
+// L_jj, turns column j into C_ij = L_ij / sqrt(L_jj), subtracts
+// C_ij conj(C_kj) from every entry (i, k) with k > j, and writes the updated
+// column j + 1 into col[(j + 1) & 1] for the next step. Returns 0, having
+// written C to m (lower triangle and real diagonal, zero above), or the
+// 1-based index of the first pivot that is not > 0 (NaN included), at which
+// the factorization stopped, leaving m unwritten.
 template <int NT>
-__device__ __forceinline__ int chol_packed(double2 *L, double *diag, int n) {
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    constexpr int NW = NT / 64;
-    int info = 0;
+__device__ __forceinline__ int chol_atom(const double2 *__restrict__ t, int n, double2 *col,
+                                         double2 *__restrict__ m) {
+    constexpr int NS = (PACKED_MAX + NT - 1) / NT;
+    int tid = threadIdx.x;
+    // opaque to the compiler, so that the slot decoding below is not hoisted
+    // out of a caller's loop (where it would hold registers throughout)
+    asm volatile("" : "+v"(tid));
+    const int ntri = n * (n + 1) / 2;
+    double2 v[NS];
+    int ik[NS];   // i << 8 | k of each slot's entry, -1 for none
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int e = s * NT + tid;
+        int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+        if (i * (i + 1) / 2 > e) --i;
+        if ((i + 1) * (i + 2) / 2 <= e) ++i;
+        ik[s] = e < ntri ? i << 8 | (e - i * (i + 1) / 2) : -1;
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int i = ik[s] >> 8, k = ik[s] & 255;
+        v[s] = ik[s] < 0 ? double2{0.0, 0.0} : t[i * n + k];
+        if (ik[s] >= 0 && k == 0) col[i] = v[s];
+    }
+    __syncthreads();
     for (int j = 0; j < n; ++j) {
-        const double dj = L[pidx(j, j)].x;
-        if (!(dj > 0.0)) {
-            info = j + 1;
-            break;
-        }
-        const double cjj = sqrt(dj);
-        if (tid == 0) diag[j] = cjj;
-        for (int i = j + 1 + tid; i < n; i += NT) {
-            double2 v = L[pidx(i, j)];
-            v.x /= cjj;
-            v.y /= cjj;
-            L[pidx(i, j)] = v;
-        }
-        __syncthreads();
-        for (int i = j + 1 + wave; i < n; i += NW) {
-            const double2 cij = L[pidx(i, j)];
-            for (int k = j + 1 + lane; k <= i; k += 64) {
-                const double2 ckj = L[pidx(k, j)];
-                double2 t = L[pidx(i, k)];
-                // t -= cij * conj(ckj)
-                t.x -= cij.x * ckj.x + cij.y * ckj.y;
-                t.y -= cij.y * ckj.x - cij.x * ckj.y;
-                L[pidx(i, k)] = t;
+        const double2 *cj = col + (j & 1) * HS_MAX_NL;
+        double2 *cn = col + ((j + 1) & 1) * HS_MAX_NL;
+        const double ljj = cj[j].x;
+        if (!(ljj > 0.0)) return j + 1;   // the same value in every thread
+        const double rs = 1.0 / sqrt(ljj);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            // decoded anew each step rather than kept decoded in registers
+            asm volatile("" : "+v"(ik[s]));
+            const int i = ik[s] >> 8, k = ik[s] & 255;
+            if (ik[s] < 0 || k < j) continue;
+            if (k == j) {
+                v[s].x *= rs;
+                v[s].y *= rs;
+            } else {
+                const double2 a = cj[i], b = cj[k];
+                const double ax = a.x * rs, ay = a.y * rs, bx = b.x * rs, by = b.y * rs;
+                // v -= C_ij conj(C_kj)
+                v[s].x -= ax * bx + ay * by;
+                v[s].y -= ay * bx - ax * by;
+                if (k == j + 1) cn[i] = v[s];
             }
         }
         __syncthreads();
     }
-    return info;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        if (ik[s] < 0) continue;
+        const int i = ik[s] >> 8, k = ik[s] & 255;
+        m[i * n + k] = k == i ? double2{v[s].x, 0.0} : v[s];
+    }
+    for (int e = tid; e < n * n; e += NT)
+        if (e % n > e / n) m[e] = double2{0.0, 0.0};
+    return 0;
 }
 
 // Preparation of atom a by one block of NT threads (every thread calls it):
 //   M2_a = 1/2 T_BB,a (Hermitian), d, sel[0..2K) rows of a; then *flag_m2
-//   (if not null) is set;
+//   (if not null) is set to 1;
 //   Cholesky of T_AA,a: M1_a = C_a (lower, zero above) on success, else
 //   T_AA,a (Hermitian); sel[2K + r] = (info != 0); info_out[a] = info; then
-//   *flag_m1 (if not null) is set.
-// L: LDS of PREP_LDS_BYTES.
+//   *flag_m1 (if not null) is set to 1 on success, 2 on failure.
+// lds: PREP_LDS_BYTES of LDS.
 template <int NT>
 __device__ __forceinline__ void prep_atom(const Atoms &at, int a, const double2 *__restrict__ T_AA,
                                           const double2 *__restrict__ T_BB,
@@ -116,8 +144,7 @@ __device__ __forceinline__ void prep_atom(const Atoms &at, int a, const double2 
                                           double2 *__restrict__ M2, double *__restrict__ d,
                                           int *__restrict__ sel, int *__restrict__ info_out,
                                           char *lds, int *flag_m2, int *flag_m1) {
-    double2 *L = reinterpret_cast<double2 *>(lds);
-    double *diag = reinterpret_cast<double *>(lds + PACKED_MAX * 16);
+    double2 *col = reinterpret_cast<double2 *>(lds);
 
     const int tid = threadIdx.x;
 
@@ -135,47 +162,15 @@ __device__ __forceinline__ void prep_atom(const Atoms &at, int a, const double2 
         sel[r0 + l] = 0;
         sel[K + r0 + l] = 0;
     }
-    if (flag_m2) publish(flag_m2);
-
-    // lower triangle of T_AA,a into LDS, eight loads in flight per thread
-    const int nn = n * n;
-    constexpr int BATCH = 8;
-    for (int e0 = 0; e0 < nn; e0 += BATCH * NT) {
-        double2 v[BATCH];
-#pragma unroll
-        for (int b = 0; b < BATCH; ++b) {
-            const int e = e0 + b * NT + tid;
-            v[b] = taa[e < nn ? e : nn - 1];   // clamped: every load in bounds
-        }
-#pragma unroll
-        for (int b = 0; b < BATCH; ++b) {
-            const int e = e0 + b * NT + tid;
-            if (e < nn) {
-                const int i = e / n, k = e - (e / n) * n;
-                if (k <= i) L[pidx(i, k)] = v[b];
-            }
-        }
-    }
-    __syncthreads();
-
-    const int info = chol_packed<NT>(L, diag, n);
+    if (flag_m2) publish(flag_m2, 1);
 
     double2 *m1 = M1 + t0;
-    if (info == 0) {
-        for (int e = tid; e < nn; e += NT) {
-            const int i = e / n, k = e % n;
-            double2 v = {0.0, 0.0};
-            if (k < i) v = L[pidx(i, k)];
-            else if (k == i) v.x = diag[i];
-            m1[e] = v;
-        }
-    } else {
-        hermitian_from_lower<NT>(taa, n, 1.0, m1);
-    }
+    const int info = chol_atom<NT>(taa, n, col, m1);
+    if (info != 0) hermitian_from_lower<NT>(taa, n, 1.0, m1);
     for (int l = tid; l < n; l += NT) sel[2 * K + r0 + l] = info != 0;
     if (tid == 0) info_out[a] = info;
-    if (flag_m1) publish(flag_m1);
-    // the LDS triangle may be reused by the caller after this barrier
+    if (flag_m1) publish(flag_m1, info != 0 ? 2 : 1);
+    // the LDS column buffers may be reused by the caller after this barrier
     __syncthreads();
 }
 
