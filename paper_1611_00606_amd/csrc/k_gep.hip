@@ -259,15 +259,21 @@ __device__ __forceinline__ double bcast(double v, int src) {
 
 // Lanes 0..15 hold the rows of a 16 x 16 Hermitian tile (lower triangle
 // used); on return the rows of its Cholesky factor. Returns 0 or the
-// 1-based index of the first pivot that is not > 0.
+// 1-based index of the first pivot that is not > 0. Each step's pivot comes
+// from lane j by readlane; 1/sqrt of it from the hardware estimate refined by
+// two Newton steps (y += y (1 - d y^2) / 2; the estimate is good to far more
+// than the 2^-13 two steps need for full precision), and sqrt(d) = d / sqrt(d);
+// the scaled entries l_kj broadcast with readlane.
 __device__ __forceinline__ int chol16(double2 (&a)[16], int lane) {
     int inf = 0;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const double d = bcast(a[j].x, j);
         if (!(d > 0.0) && inf == 0) inf = j + 1;
-        const double c = sqrt(d);
-        const double rc = 1.0 / c;
+        double rc = __builtin_amdgcn_rsq(d);
+        rc = fma(0.5 * rc, fma(-d * rc, rc, 1.0), rc);
+        rc = fma(0.5 * rc, fma(-d * rc, rc, 1.0), rc);
+        const double c = d * rc;
         a[j] = lane == j ? double2{c, 0.0} : double2{a[j].x * rc, a[j].y * rc};
 #pragma unroll
         for (int k = j + 1; k < 16; ++k) {   // a_rk -= l_rj conj(l_kj)
