@@ -77,6 +77,7 @@ struct MmJob {
     int k0, k1;               // contraction rows of P and Q
     int ntr, ntc;             // tile rows / columns of the rectangle
     int start;                // first block of this job
+    int flags;                // MM_* of this job
 };
 constexpr int MM_JOBS = 32;
 
@@ -85,7 +86,7 @@ struct MmArgs {
     const double2 *P2, *Q2;   // second term, same rectangle and contraction range
     double2 *C;
     int N;                    // leading dimension of P, Q, C
-    int flags, op;
+    int op;
     int njobs;
     int total;                // tiles over all jobs (blocks loop over them)
     MmJob job[MM_JOBS];
@@ -98,12 +99,12 @@ struct MmArgs {
 template <int NSEG, bool G3>
 __device__ __forceinline__ void mm_tile(const MmArgs &args, int tile, double2 *lds) {
     using Cfg = MmCfg;
-    const int flags = args.flags;
     const int N = args.N;
     int jb = 0;
 #pragma unroll
     for (int t = 1; t < MM_JOBS; ++t)
         if (t < args.njobs && tile >= args.job[t].start) jb = t;
+    const int flags = args.job[jb].flags;
     const int bid = tile - args.job[jb].start;
     const int ntr = args.job[jb].ntr, ntc = args.job[jb].ntc;
     const int i0 = args.job[jb].i0, i1 = args.job[jb].i1;
@@ -763,9 +764,9 @@ int sched_check(const Sched &sc, int N, std::string &report) {
 void sched_mm(const Gep &g, const MmArgs &a) {
     using Cfg = MmCfg;
     SchedOp &op = g_sched->launch(g.st, a.P2 ? "k_gep_mm<2>" : "k_gep_mm<1>");
-    const int flags = a.flags;
     for (int jb = 0; jb < a.njobs; ++jb) {
         const MmJob &j = a.job[jb];
+        const int flags = j.flags;
         for (int ti = 0; ti < j.ntr; ++ti)
             for (int tj = 0; tj < j.ntc; ++tj) {
                 if ((flags & MM_UPPER) && tj < ti) continue;
@@ -789,10 +790,12 @@ void sched_mm(const Gep &g, const MmArgs &a) {
     }
 }
 
-// Products over the rectangles r[0 .. n), up to MM_JOBS per launch.
+// Products over the rectangles r[0 .. n), up to MM_JOBS per launch, with
+// the flags rflags[t] of each (or flags for all when rflags is null); the
+// blocks take the rectangles in the order given.
 hipError_t mm_batch(const Gep &g, const double2 *P, const double2 *Q, double2 *C, const Rect *r,
                     int n, int flags, int op, const double2 *P2 = nullptr,
-                    const double2 *Q2 = nullptr) {
+                    const double2 *Q2 = nullptr, const int *rflags = nullptr) {
     using Cfg = MmCfg;
     for (int b = 0; b < n; b += MM_JOBS) {
         MmArgs a = {};
@@ -802,7 +805,6 @@ hipError_t mm_batch(const Gep &g, const double2 *P, const double2 *Q, double2 *C
         a.Q2 = Q2;
         a.C = C;
         a.N = g.N;
-        a.flags = flags;
         a.op = op;
         long long nblk = 0;
         for (int t = b; t < n && t < b + MM_JOBS; ++t) {
@@ -817,7 +819,8 @@ hipError_t mm_batch(const Gep &g, const double2 *P, const double2 *Q, double2 *C
             j.ntr = (j.i1 - j.i0 + Cfg::BM - 1) / Cfg::BM;
             j.ntc = (j.j1 - j.j0 + Cfg::BN - 1) / Cfg::BN;
             j.start = (int)nblk;
-            if (flags & (MM_LOWER | MM_UPPER)) {
+            j.flags = rflags ? rflags[t] : flags;
+            if (j.flags & (MM_LOWER | MM_UPPER)) {
                 if (j.i0 != j.j0 || j.i1 != j.j1) return hipErrorInvalidValue;
                 nblk += (long long)j.ntr * (j.ntr + 1) / 2;
             } else {
@@ -1084,20 +1087,22 @@ hipError_t v_cols(const Gep &g, const double2 *H, int c0, int c1) {
     return mm(g, H, g.MH, g.LH, 0, g.N, c0, c1, 0, g.N, MM_QU, OP_STORE);
 }
 
-// WH[:, c0:c1) (rows i <= j)
+// WH[:, c0:c1) (rows i <= j): the rows above the block (longer contractions)
+// and the block's upper triangle in one launch
 hipError_t wh_cols(const Gep &g, int c0, int c1) {
     const int N = g.N;
-    GEP_TRY(mm(g, g.HL, g.MH, g.LH, 0, c0, c0, c1, 0, N, MM_PL | MM_QU, OP_STORE));
-    return mm(g, g.HL, g.MH, g.LH, c0, c1, c0, c1, 0, N, MM_PL | MM_QU | MM_UPPER, OP_STORE);
+    const Rect r[2] = {{0, c0, c0, c1, 0, N}, {c0, c1, c0, c1, 0, N}};
+    const int f[2] = {MM_PL | MM_QU, MM_PL | MM_QU | MM_UPPER};
+    return mm_batch(g, g.HL, g.MH, g.LH, r, 2, 0, OP_STORE, nullptr, nullptr, f);
 }
 
-// lower triangle of Ht, rows [r0, r1)
+// lower triangle of Ht, rows [r0, r1): the triangle (contractions up to
+// r1) and then the rows' columns left of it (up to r0) in one launch
 hipError_t her2k_rows(const Gep &g, double2 *Ht, int r0, int r1) {
     const int N = g.N;
-    const Rect rect = {r0, r1, 0, r0, 0, N};
-    const Rect tri = {r0, r1, r0, r1, 0, N};
-    GEP_TRY(mm_batch(g, g.LH, g.MH, Ht, &rect, 1, MM_QU, OP_STORE, g.MH, g.LH));
-    return mm_batch(g, g.LH, g.MH, Ht, &tri, 1, MM_QU | MM_LOWER, OP_STORE, g.MH, g.LH);
+    const Rect r[2] = {{r0, r1, r0, r1, 0, N}, {r0, r1, 0, r0, 0, N}};
+    const int f[2] = {MM_QU | MM_LOWER, MM_QU};
+    return mm_batch(g, g.LH, g.MH, Ht, r, 2, 0, OP_STORE, g.MH, g.LH, f);
 }
 
 }  // namespace
