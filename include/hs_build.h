@@ -140,7 +140,7 @@ typedef enum {
 /* Tile shapes of the batched per-atom stage (see hs_options.batch): shape id
  * -> (BM rows of an atom's N_L, BN columns of N_G) per tile, listed by
  * hs_tile_config. */
-#define HS_NUM_TILE_CONFIGS 6
+#define HS_NUM_TILE_CONFIGS 8
 
 /* Tile shape id for each N_L (entry [N_L], 1 <= N_L <= HS_MAX_NL; entry 0
  * unused), as filled by hs_autotune_atoms. */

@@ -31,7 +31,7 @@ HS_SPLIT_BF16 = 4
 HS_SPLIT_I8_CRT = 5
 HS_MAX_NL = 128
 HS_NUM_PHASE_EVENTS = 5
-HS_NUM_TILE_CONFIGS = 6
+HS_NUM_TILE_CONFIGS = 8
 HS_STATIC_SCRATCH_BYTES = 256 << 20
 HS_ADMIT_FIFO = 0
 HS_ADMIT_BYPASS = 1

@@ -35,8 +35,9 @@ def tuning_from_table(table: Dict[int, int]) -> B.hs_tuning:
 
 def default_shape(nl: int) -> int:
     """The library's built-in shape id for N_L (used when no table is given):
-    the 128-column tile with the fewest rows (32, 64, 96, 128) covering N_L."""
-    return 0 if nl <= 32 else 1 if nl <= 64 else 2 if nl <= 96 else 3
+    the tile with the fewest rows (32, 64, 96, 128) covering N_L, 128 columns
+    wide except for 96 rows (192 columns)."""
+    return 0 if nl <= 32 else 1 if nl <= 64 else 6 if nl <= 96 else 3
 
 
 def _shape_id(bm_bn: str) -> Optional[int]:

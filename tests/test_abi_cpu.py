@@ -180,19 +180,20 @@ def test_tile_configs():
     assert all(s is not None for s in shapes)
     assert len(set(shapes)) == len(shapes)
     for bm, bn in shapes:
-        assert bm % 32 == 0 and bm <= 128 and bn in (128, 256)
-    # the built-in choice: the fewest 128-column rows that cover N_L
+        assert bm % 32 == 0 and bm <= 128 and bn in (128, 192, 256)
+    # the built-in choice: the fewest rows that cover N_L, 192 columns for 96
+    # rows, else 128
     from paper_1611_00606_amd.tuning import default_shape as ds
     for v in range(1, 129):
         bm, bn = shapes[ds(v)]
-        assert bn == 128 and bm >= v and bm - 32 < v
+        assert bm >= v and bm - 32 < v and bn == (192 if bm == 96 else 128)
     assert P.hs_tile_config(-1) is None and P.hs_tile_config(P.HS_NUM_TILE_CONFIGS) is None
     from paper_1611_00606_amd.tuning import default_shape, tuning_from_table
     assert all(0 <= default_shape(v) < P.HS_NUM_TILE_CONFIGS for v in range(1, 129))
     t = tuning_from_table({16: 0, 121: 5})
     assert t.cfg[16] == 0 and t.cfg[121] == 5 and t.cfg[49] == default_shape(49)
     with pytest.raises(ValueError):
-        tuning_from_table({16: 6})
+        tuning_from_table({16: P.HS_NUM_TILE_CONFIGS})
     with pytest.raises(ValueError):
         tuning_from_table({0: 1})
 

@@ -72,8 +72,10 @@ def test_batch_parity(name):
     assert np.array_equal(H, H0) and np.array_equal(S, S0) and np.array_equal(info, info0)
 
 
-@pytest.mark.parametrize("shape", range(6))
+@pytest.mark.parametrize("shape", range(8))
 def test_every_tile_shape_matches_unbatched(shape):
+    from paper_1611_00606_amd import HS_NUM_TILE_CONFIGS
+    assert HS_NUM_TILE_CONFIGS == 8
     p = make_problem(7, [16, 49, 81, 121, 5, 128, 33], 523, seed=12, fail_atoms=[1],
                      planted={2: 30})
     r0 = _run(p, batch=0)
@@ -137,11 +139,11 @@ def test_batch_in_context():
 
 
 def test_autotuner():
-    from paper_1611_00606_amd import hs_autotune_atoms, hs_tile_config
+    from paper_1611_00606_amd import HS_NUM_TILE_CONFIGS, hs_autotune_atoms, hs_tile_config
     vals = [16, 121, 16]
     t, ms = hs_autotune_atoms(vals, 1000, reps=2)
     print("  autotune ms", ms.tolist(), flush=True)
-    assert ms.shape == (3, 6) and np.all(ms > 0) and np.all(np.isfinite(ms))
+    assert ms.shape == (3, HS_NUM_TILE_CONFIGS) and np.all(ms > 0) and np.all(np.isfinite(ms))
     assert np.array_equal(ms[0], ms[2])
     for i, v in enumerate(vals):
         assert t.cfg[v] == int(np.argmin(ms[i]))
