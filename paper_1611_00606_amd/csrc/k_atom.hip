@@ -94,7 +94,8 @@ hipError_t launch_atom_cfg(const Atoms &at, int n_g, const double2 *A, const dou
 }  // namespace
 
 // Row tile of 32, 64, 96 or 128 (the smallest that covers the largest N_L),
-// 128 columns.
+// 128 columns (192 for the 96-row tile, as in the batched launch's
+// built-in choice).
 hipError_t launch_atom(const Atoms &at, int n_g, const double2 *A, const double2 *B,
                        const double2 *T_AB, const double2 *M1, const double2 *M2,
                        const int *sel, double2 *Z, double2 *W, hipStream_t st) {
@@ -103,7 +104,7 @@ hipError_t launch_atom(const Atoms &at, int n_g, const double2 *A, const double2
     if (at.max_nl <= 64)
         return launch_atom_cfg<AtomCfg<2, 2, 16>>(at, n_g, A, B, T_AB, M1, M2, sel, Z, W, st);
     if (at.max_nl <= 96)
-        return launch_atom_cfg<AtomCfg<3, 2, 16>>(at, n_g, A, B, T_AB, M1, M2, sel, Z, W, st);
+        return launch_atom_cfg<AtomCfg<3, 3, 8>>(at, n_g, A, B, T_AB, M1, M2, sel, Z, W, st);
     return launch_atom_cfg<AtomCfg<4, 2, 16>>(at, n_g, A, B, T_AB, M1, M2, sel, Z, W, st);
 }
 
