@@ -186,9 +186,9 @@ typedef struct {
        and every atom's Z_a and W_a tiles, each atom with the tile shape of
        its N_L. Same results up to rounding order. */
     int batch;
-    /* HOST hs_tuning or NULL (built-in shapes: 32, 64, 96 or 128 rows by 128
-       columns, the fewest rows that cover N_L). Used when batch = 1; every
-       N_L in use must map to an id < HS_NUM_TILE_CONFIGS. */
+    /* HOST hs_tuning or NULL (built-in shapes: 32, 64, 96 or 128 rows, the
+       fewest that cover N_L, by 128 columns, 192 for 96 rows). Used when
+       batch = 1; every N_L in use must map to an id < HS_NUM_TILE_CONFIGS. */
     const hs_tuning *tuning;
 } hs_options;
 
